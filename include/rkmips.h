@@ -1,0 +1,211 @@
+/*
+ * rkmips.h: C ABI of the MI355X (gfx950) exact reverse k-MIPS library.
+ *
+ * Method: Simpfer (Amagata & Hara, "Reverse Maximum Inner Product Search",
+ * RecSys 2021).  Given users Q (n x d), items P (m x d), a query item q and k,
+ * the reverse k-MIPS result is every user u for which q is among the k best
+ * items of u over P u {q} (Definition 2, Section 2).  Ties go to q: u is a
+ * member iff fewer than k items p in P have f(p,u) > f(q,u).
+ *
+ * Exactness contract.  f(x,y) is the inner product of the float32 inputs
+ * accumulated in double precision in index order (i = 0..d-1).  Every result
+ * set returned by this library equals the set defined with that f, whatever
+ * precision the bulk arithmetic runs in: decisions taken in float32 or
+ * bfloat16 are taken only when a rigorous error bound certifies them, and
+ * every other user is decided by a float64 recomputation of f on the device.
+ *
+ * Conventions for every entry point:
+ *  - All matrices are row-major, float32, contiguous; row r of Q is user r.
+ *  - Result ids are original row indices of Q, int32, strictly ascending.
+ *  - Host pointers are borrowed for the duration of the call only.  "_dev"
+ *    entry points take device pointers (HIP device memory of the index's
+ *    device) and a hipStream_t passed as void* (NULL = the index's own
+ *    stream); they enqueue work and return without waiting unless stated.
+ *  - On any error nothing is written to outputs except where stated, no
+ *    partial index is left behind, and rk_last_error() returns a message.
+ *  - An rk_index is used by one host thread at a time.
+ */
+#ifndef RKMIPS_H
+#define RKMIPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rk_index rk_index;
+
+typedef enum {
+    RK_OK = 0,
+    RK_E_INVAL = 1,  /* null pointer, n < 0, m < 0, d < 1, k < 1, k_max < 1,
+                        non-finite input or |x_i| >= 2^40, bad option */
+    RK_E_KMAX = 2,   /* k > k_max of the index and auto_rebuild is off */
+    RK_E_NOMEM = 3,  /* device allocation failed; nothing was created */
+    RK_E_TRUNC = 4,  /* output capacity too small; counts hold true sizes */
+    RK_E_DEVICE = 5  /* HIP runtime error; see rk_last_error() */
+} rk_status;
+
+typedef enum {
+    RK_FP32 = 0,     /* bulk inner products in float32 (VALU or FP32 MFMA) */
+    RK_BF16 = 1      /* bulk inner products from bfloat16 copies of Q, P and q
+                        with float32 accumulation (BF16 MFMA); users inside
+                        the bf16 error margin are recomputed in float64 */
+} rk_precision;
+
+/* Options of rk_build_index.  Call rk_build_opts_default() first. */
+typedef struct {
+    int32_t precision;    /* rk_precision */
+    int32_t lb_items;     /* |P'|, the number of largest-norm items the
+                             lower-bound arrays are taken over (Definition 4,
+                             Algorithm 1).  0 = all of P: the arrays then hold
+                             each user's exact k_max largest inner products
+                             and every decision is a single certified compare.
+                             k_max..m = the paper's P' prefix (its experiments
+                             use O(k_max)); values above m are clamped to m. */
+    int32_t block_size;   /* users per block (Definition 5); 0 or 64 only:
+                             one block is one 64-lane wavefront */
+    int32_t device;       /* HIP device ordinal */
+    double margin_rel;    /* extra relative margin: the certified tests use
+                             max(margin_rel, rigorous bound) * |u||q| */
+    int32_t cand_cap;     /* 0 = default.  Per-user capacity of the candidate
+                             list in the full-table build; users that overflow
+                             it are recomputed exactly over all of P (a test
+                             hook for that path) */
+    int32_t auto_rebuild; /* nonzero: a query with k > k_max first rebuilds
+                             the lower-bound arrays with k_max = k (the
+                             paper's rule for k > k_max, Section 4.1) */
+    int32_t reserved[6];
+} rk_build_opts;
+
+/* Counters and sizes of an index.  Query counters accumulate over every
+ * query since the build or the last rk_index_reset_counters(). */
+typedef struct {
+    int64_t n, m;
+    int32_t d, k_max, lb_items, block_size, n_blocks, precision;
+    int64_t footprint_bytes;   /* device bytes owned by the index */
+    double build_ms;           /* wall time of the last (re)build */
+    int64_t build_cand_total;  /* candidates refined in float64 (full table) */
+    int64_t build_cand_overflow_users;
+    int64_t rebuilds;
+    int64_t queries;
+    int64_t blocks_visited;    /* (block, query) pairs tested with Lemma 3 */
+    int64_t blocks_pruned;     /* ... and pruned by it */
+    int64_t users_evaluated;   /* u.q computed (users of unpruned blocks) */
+    int64_t lemma1_no;         /* certified no by Lemma 1 */
+    int64_t lemma2_yes;        /* certified yes by Lemma 2 */
+    int64_t table_yes;         /* certified yes by the exact k-th value */
+    int64_t survivors;         /* users sent to the linear scan */
+    int64_t scan_items;        /* item inner products computed in scans */
+    int64_t rechecks;          /* users decided by float64 recomputation */
+    int64_t results;           /* total result-set sizes */
+    int64_t reserved[8];
+} rk_stats;
+
+/* Index fields readable with rk_index_export (sorted = descending norm). */
+typedef enum {
+    RK_F_PERM_Q = 0,   /* int32 [n]: original user id of sorted position i */
+    RK_F_PERM_P = 1,   /* int32 [m]: original item id of sorted position j */
+    RK_F_SQNORM_Q = 2, /* double [n], original order: sum x_i^2 (index order) */
+    RK_F_SQNORM_P = 3, /* double [m], original order */
+    RK_F_NORM_Q = 4,   /* float [n], sorted: norm rounded upward */
+    RK_F_NORM_P = 5,   /* float [m], sorted: norm rounded upward */
+    RK_F_L64 = 6,      /* double [k_max][n], sorted users: L_i^j exactly */
+    RK_F_L32 = 7,      /* float [k_max][n]: L_i^j rounded downward */
+    RK_F_LB = 8,       /* float [k_max][n_blocks]: block minima L^j(B) */
+    RK_F_BNORM = 9     /* float [n_blocks]: first (largest) norm of a block */
+} rk_field;
+
+/* Per-user decision classes written by rk_reverse_kmips_trace. */
+typedef enum {
+    RK_C_BLOCK_NO = 0,   /* block pruned by Lemma 3 */
+    RK_C_LEMMA1_NO = 1,  /* certified no by Lemma 1 */
+    RK_C_LEMMA2_YES = 2, /* certified yes by Lemma 2 */
+    RK_C_TABLE_YES = 3,  /* certified yes by the exact k-th value */
+    RK_C_SCAN_NO = 4,    /* linear scan: k items certified to beat q */
+    RK_C_SCAN_YES = 5,   /* linear scan: certified fewer than k */
+    RK_C_RECHECK_NO = 6, /* float64 recomputation: no */
+    RK_C_RECHECK_YES = 7 /* float64 recomputation: yes */
+} rk_class;
+
+void rk_build_opts_default(rk_build_opts *opts);
+
+/* Offline pre-processing, Algorithm 1 (Section 4.1): norms, descending norm
+ * sort of Q and P, lower-bound arrays over P' (Definition 4), blocks with
+ * their minima (Definition 5, Equation (1)).  Copies Q and P to the device;
+ * the index owns every device buffer until rk_index_free.  n = 0 and m = 0
+ * are allowed.  opts may be NULL (defaults).  Synchronous. */
+rk_status rk_build_index(const float *Q, int64_t n, const float *P, int64_t m,
+                         int32_t d, int32_t k_max, const rk_build_opts *opts,
+                         rk_index **out);
+
+/* Same, from device pointers (not retained).  Synchronous. */
+rk_status rk_build_index_dev(const float *Q_dev, int64_t n, const float *P_dev,
+                             int64_t m, int32_t d, int32_t k_max,
+                             const rk_build_opts *opts, rk_index **out);
+
+/* One query, Algorithm 3 with Algorithm 2 (Sections 4.2-4.3).  q: host,
+ * d floats.  Writes min(count, cap) ascending ids and *count = true size;
+ * returns RK_E_TRUNC when count > cap.  k > m returns every user.
+ * Synchronous. */
+rk_status rk_reverse_kmips(rk_index *idx, const float *q, int32_t k,
+                           int32_t *ids, int64_t cap, int64_t *count);
+
+/* One query on device buffers: q_dev (d floats), ids_dev (cap ints),
+ * count_dev (one int64, receives the true size; ids beyond cap are dropped).
+ * Enqueued on stream; returns without waiting. */
+rk_status rk_reverse_kmips_dev(rk_index *idx, const float *q_dev, int32_t k,
+                               int32_t *ids_dev, int64_t cap,
+                               int64_t *count_dev, void *stream);
+
+/* A batch of nq queries of mixed k.  qs: host [nq][d]; ks: host [nq].
+ * Result in CSR form: offsets[nq+1] (host, offsets[0] = 0) and ids (host,
+ * cap ints).  Returns RK_E_TRUNC when offsets[nq] > cap (offsets are still
+ * complete).  Synchronous. */
+rk_status rk_reverse_kmips_batch(rk_index *idx, const float *qs, int64_t nq,
+                                 const int32_t *ks, int64_t *offsets,
+                                 int32_t *ids, int64_t cap);
+
+/* Batch on device buffers: qs_dev [nq][d], ks_host [nq] (host: validated
+ * before anything is enqueued), offsets_dev (nq+1 int64), ids_dev (cap
+ * int32; ids beyond cap are dropped while offsets stay exact).  Enqueued on
+ * stream; returns without waiting. */
+rk_status rk_reverse_kmips_batch_dev(rk_index *idx, const float *qs_dev,
+                                     int64_t nq, const int32_t *ks_host,
+                                     int64_t *offsets_dev, int32_t *ids_dev,
+                                     int64_t cap, void *stream);
+
+/* One query with per-user decision classes (rk_class, one byte per user,
+ * indexed by original id; users never evaluated keep RK_C_BLOCK_NO) and
+ * optionally the bulk-precision u.q (float per original id; NaN where not
+ * computed).  shat may be NULL.  Host buffers.  Synchronous. */
+rk_status rk_reverse_kmips_trace(rk_index *idx, const float *q, int32_t k,
+                                 uint8_t *cls, float *shat);
+
+/* Counters are off by default (they cost atomics on the query path). */
+rk_status rk_index_set_counting(rk_index *idx, int32_t on);
+rk_status rk_index_stats(const rk_index *idx, rk_stats *out);
+rk_status rk_index_reset_counters(rk_index *idx);
+
+/* Copy one index field (rk_field) into host memory of `bytes` bytes; the
+ * size must match the field exactly. */
+rk_status rk_index_export(const rk_index *idx, int32_t field, void *dst,
+                          int64_t bytes);
+
+/* Rebuild the lower-bound arrays and blocks with a new k_max from the
+ * device-resident sorted copies (Section 4.1, k > k_max).  Synchronous. */
+rk_status rk_index_rebuild(rk_index *idx, int32_t k_max);
+
+/* Device bytes an index with these sizes and options would own. */
+int64_t rk_index_footprint(int64_t n, int64_t m, int32_t d, int32_t k_max,
+                           const rk_build_opts *opts);
+
+void rk_index_free(rk_index *idx);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *rk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RKMIPS_H */

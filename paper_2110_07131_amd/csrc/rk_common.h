@@ -1,0 +1,108 @@
+// Shared definitions of the reverse k-MIPS HIP library (gfx950, wave64).
+//
+// Device layouts (users and items both sorted by descending norm, Algorithm 1):
+//   tiled fp32   X_t[tile][c][64]            element (row r, coord c) at
+//                (r/64)*D*64 + c*64 + r%64, D = d.  One tile of 64 rows is one
+//                user block (Definition 5) = one wavefront; a fixed coordinate
+//                of 64 consecutive rows is one coalesced 256-byte segment.
+//   tiled bf16   X_b[tile][g][64][8]         groups of 8 coordinates, 16 bytes
+//                per (row, group), D padded with zeros to a multiple of 16.
+//   row-major    P_row[j][c]                 sorted items (float64 rechecks).
+//   bound tables L32/L64[j][r]               j-th lower bound of sorted user r;
+//                a fixed j over consecutive users is contiguous.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rkmips.h"
+
+namespace rk {
+
+constexpr int TILE = 64;  // users per block == items per tile == wave size
+
+__host__ __device__ inline int64_t tix(int64_t r, int c, int d) {
+  return (r / TILE) * (int64_t)d * TILE + (int64_t)c * TILE + (r % TILE);
+}
+
+// float32 rounded toward -inf / +inf from a double (exact directed rounding).
+__host__ __device__ inline float f32_down(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = nextafterf(f, -INFINITY);
+  return f;
+}
+__host__ __device__ inline float f32_up(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = nextafterf(f, INFINITY);
+  return f;
+}
+// Smallest float strictly above x (x finite or -inf).
+__host__ __device__ inline float f32_next_up(float x) { return nextafterf(x, INFINITY); }
+
+// float32 -> bfloat16 bits, round to nearest even (finite inputs).
+__host__ __device__ inline uint16_t bf16_bits(float x) {
+  uint32_t b;
+  memcpy(&b, &x, 4);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+  uint32_t b = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &b, 4);
+  return f;
+}
+__host__ __device__ inline float bf16_round(float x) { return bf16_to_f32(bf16_bits(x)); }
+
+// Read-only view of a device-resident index, passed to kernels by value.
+struct DevIndex {
+  int64_t n, m;          // users, items
+  int64_t n_pad, m_pad;  // rounded up to TILE
+  int32_t d, d16;        // dimension; bf16 padded dimension (multiple of 16)
+  int32_t kmax, nB, mB;  // k_max; user blocks; item tiles
+  int32_t lb_items;      // |P'|
+  int32_t exact;         // 1 if L holds the exact k_max largest values over P
+  int32_t bf16;          // 1 if the bulk products use the bf16 copies
+  const float* Qt;       // tiled fp32 users
+  const uint16_t* Qb;    // tiled bf16 users (bf16 mode)
+  const float* normQ;    // [n_pad] norm rounded up (0 for padding)
+  const int32_t* permQ;  // [n] original id of sorted user
+  const float* Pt;       // tiled fp32 items
+  const uint16_t* Pb;    // tiled bf16 items (bf16 mode)
+  const float* Prow;     // [m][d] sorted items, row-major
+  const float* normP;    // [m_pad] norm rounded up (0 for padding)
+  const float* L32;      // [kmax][n_pad] lower bounds rounded down
+  const double* L64;     // [kmax][n_pad] lower bounds, exact
+  const float* LB;       // [kmax][nB] block minima of L32
+  const float* bnorm;    // [nB] norm of the first user of each block
+  // Certified-comparison constants (see margin()):
+  float eps_rel;         // relative bound on |approx u.x - f(x,u)| / (|u||x|)
+  float eps_abs;         // absolute slack (underflow)
+  float cs_inflate;      // 1 + gamma64_d + slack: f(p,u) <= cs_inflate*|u|^*|p|^
+};
+
+// |approx - f| <= margin(|u|^, |x|^) for every bulk inner product.
+__device__ __forceinline__ float margin(const DevIndex& ix, float nu, float nx) {
+  return ix.eps_rel * (nu * nx) + ix.eps_abs;
+}
+
+// Per-query device workspace.
+struct QueryWS {
+  uint32_t* rbits;          // [ceil(n/32)] result bits by original id; all
+                            // zero between queries (finalize clears them)
+  int32_t* surv_idx;        // [n] survivors for the linear scan (sorted idx)
+  float* surv_s;            // [n] their approximate u.q
+  int32_t* rchk_idx;        // [n] users for float64 recomputation
+  int32_t* cnt;             // [4]: survivors, rechecks, -, -  (reset by finalize)
+  float* qnorm;             // [1] |q| rounded up (written by the filter)
+  unsigned long long* ctr;  // [16] statistics counters or nullptr
+  uint8_t* trace_cls;       // [n] by original id, or nullptr
+  float* trace_s;           // [n] by original id, or nullptr
+};
+
+// Counter slots (statistics).
+enum Ctr {
+  C_BLOCKS = 0, C_PRUNED, C_USERS, C_L1NO, C_L2YES, C_TYES, C_SURV, C_SCAN,
+  C_RCHK, C_RES, C_NCTR
+};
+
+}  // namespace rk

@@ -1,0 +1,671 @@
+// Host runtime and C ABI (include/rkmips.h).  Owns every device buffer of an
+// index, validates arguments before any device work, sequences the build
+// (Algorithm 1) and query (Algorithms 2-3) kernels on the index's stream.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "rk_kernels.h"
+
+using namespace rk;
+
+namespace {
+
+thread_local std::string g_err;
+
+rk_status fail(rk_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPTRY(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(e_ == hipErrorOutOfMemory ? RK_E_NOMEM : RK_E_DEVICE,               \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+  } while (0)
+
+constexpr int64_t kSeedItems = 1024;  // exact float64 prefix that seeds the full build
+constexpr int32_t kMaxD = 512;
+constexpr int32_t kMaxKmax = 128;
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+double gamma_(double k, double u) { return k * u / (1.0 - k * u); }
+
+// Rigorous relative bounds |approx u.x - f(x,u)| <= eps * |u| |x| (see the
+// error analysis in the design notes): float32 accumulation of d exact or
+// once-rounded products in any order, plus the float64 rounding of f itself,
+// plus slack for evaluating the certified tests in float32.
+double eps_fp32(int d) {
+  return gamma_(d + 2, 0x1p-24) + gamma_(d, 0x1p-53) + 16 * 0x1p-24;
+}
+double eps_bf16(int d) {
+  const double r = (1 + 0x1p-8) * (1 + 0x1p-8) * (1 + gamma_(d + 2, 0x1p-24)) - 1;
+  return r + gamma_(d, 0x1p-53) + 16 * 0x1p-24;
+}
+
+}  // namespace
+
+struct rk_index {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  rk_build_opts opts{};
+  DevIndex ix{};
+  double eps32 = 0;  // float32 bound (build candidate pass)
+  std::vector<void*> dbufs;
+  std::vector<void*> hbufs;
+  size_t footprint = 0;
+  // owned device arrays
+  float *Qt = nullptr, *normQ = nullptr, *Pt = nullptr, *Prow = nullptr, *normP = nullptr;
+  uint16_t *Qb = nullptr, *Pb = nullptr;
+  int32_t *permQ = nullptr, *permP = nullptr;
+  double *s2Q = nullptr, *s2P = nullptr, *L64 = nullptr;
+  float *L32 = nullptr, *LB = nullptr, *bnorm = nullptr;
+  // query workspace
+  QueryWS ws{};
+  float* q_dev = nullptr;
+  int32_t* ids_dev = nullptr;
+  int64_t* count_dev = nullptr;
+  unsigned long long* ctr_dev = nullptr;
+  bool counting = false;
+  // pinned host staging (ids/count are mapped: the finalize kernel writes them)
+  float* q_host = nullptr;
+  int32_t* ids_host = nullptr;
+  int64_t* count_host = nullptr;
+  int32_t* ids_host_dev = nullptr;
+  int64_t* count_host_dev = nullptr;
+  // build statistics
+  double build_ms = 0;
+  int64_t cand_total = 0, cand_ovf = 0, rebuilds = 0;
+  int64_t queries = 0;
+
+  ~rk_index() {
+    if (device >= 0) (void)hipSetDevice(device);
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* p : dbufs) (void)hipFree(p);
+    for (void* p : hbufs) (void)hipHostFree(p);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+
+  template <typename T>
+  hipError_t dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e == hipSuccess) {
+      dbufs.push_back(*p);
+      footprint += count * sizeof(T);
+    }
+    return e;
+  }
+  void dfree(void* p) {
+    auto it = std::find(dbufs.begin(), dbufs.end(), p);
+    if (it != dbufs.end()) {
+      dbufs.erase(it);
+      (void)hipFree(p);
+    }
+  }
+};
+
+namespace {
+
+rk_status check_opts(const rk_build_opts& o) {
+  if (o.precision != RK_FP32 && o.precision != RK_BF16) return fail(RK_E_INVAL, "precision must be RK_FP32 or RK_BF16");
+  if (o.lb_items < 0) return fail(RK_E_INVAL, "lb_items must be >= 0");
+  if (o.block_size != 0 && o.block_size != TILE) return fail(RK_E_INVAL, "block_size must be 0 or 64");
+  if (!(o.margin_rel >= 0.0) || !std::isfinite(o.margin_rel) || o.margin_rel >= 0.5)
+    return fail(RK_E_INVAL, "margin_rel must be finite, >= 0 and < 0.5");
+  if (o.cand_cap < 0) return fail(RK_E_INVAL, "cand_cap must be >= 0");
+  if (o.device < 0) return fail(RK_E_INVAL, "device must be >= 0");
+  return RK_OK;
+}
+
+rk_status check_sizes(int64_t n, int64_t m, int32_t d, int32_t k_max) {
+  if (n < 0 || m < 0) return fail(RK_E_INVAL, "n and m must be >= 0");
+  if (n > INT32_MAX - 64 || m > INT32_MAX - 64) return fail(RK_E_INVAL, "n and m must fit int32 ids");
+  if (d < 1 || d > kMaxD) return fail(RK_E_INVAL, "d must be in [1, 512]");
+  if (k_max < 1 || k_max > kMaxKmax) return fail(RK_E_INVAL, "k_max must be in [1, 128]");
+  return RK_OK;
+}
+
+bool host_values_ok(const float* x, int64_t count) {
+  for (int64_t i = 0; i < count; ++i)
+    if (!(std::fabs(x[i]) < 1099511627776.0f)) return false;
+  return true;
+}
+
+// Build the lower-bound arrays and blocks for the index's current k_max from
+// the sorted device copies (Algorithm 1, lower-bound arrays and blocks).
+rk_status build_bounds(rk_index* h) {
+  DevIndex& ix = h->ix;
+  hipStream_t s = h->stream;
+  const int64_t lb = ix.lb_items;
+  HIPTRY(h->dalloc(&h->L64, (size_t)ix.kmax * ix.n_pad));
+  HIPTRY(h->dalloc(&h->L32, (size_t)ix.kmax * ix.n_pad));
+  HIPTRY(h->dalloc(&h->LB, (size_t)ix.kmax * ix.nB));
+  HIPTRY(h->dalloc(&h->bnorm, (size_t)ix.nB));
+  ix.L64 = h->L64;
+  ix.L32 = h->L32;
+  ix.LB = h->LB;
+  ix.bnorm = h->bnorm;
+  h->cand_total = 0;
+  h->cand_ovf = 0;
+  if (ix.n_pad > 0) {
+    if (lb <= kSeedItems) {
+      launch_lb_exact(ix, lb, h->L64, h->L32, nullptr, s);
+      HIPTRY(hipGetLastError());
+    } else {
+      // Long prefix: exact seed over the first kSeedItems items, one MFMA pass
+      // over [0, lb) keeping candidates, float64 refine of the candidates.
+      DevIndex bx = ix;
+      bx.eps_rel = (float)h->eps32;  // the candidate pass runs in float32
+      const int32_t cap = h->opts.cand_cap > 0 ? h->opts.cand_cap : std::max(128, 2 * ix.kmax + 64);
+      float* t0 = nullptr;
+      int32_t *cand = nullptr, *ccount = nullptr, *ovf = nullptr, *novf = nullptr;
+      HIPTRY(hipMalloc(&t0, ix.n_pad * sizeof(float)));
+      std::vector<void*> tmp{t0};
+      auto cleanup = [&]() { for (void* p : tmp) (void)hipFree(p); };
+      hipError_t e = hipMalloc(&cand, (size_t)ix.n_pad * cap * sizeof(int32_t));
+      if (e == hipSuccess) { tmp.push_back(cand); e = hipMalloc(&ccount, ix.n_pad * sizeof(int32_t)); }
+      if (e == hipSuccess) { tmp.push_back(ccount); e = hipMalloc(&ovf, ix.n_pad * sizeof(int32_t)); }
+      if (e == hipSuccess) { tmp.push_back(ovf); e = hipMalloc(&novf, sizeof(int32_t)); }
+      if (e == hipSuccess) { tmp.push_back(novf); e = hipMemsetAsync(novf, 0, sizeof(int32_t), s); }
+      if (e != hipSuccess) { cleanup(); HIPTRY(e); }
+      launch_lb_exact(bx, kSeedItems, nullptr, nullptr, t0, s);
+      launch_lb_candidates(bx, lb, t0, cap, cand, ccount, s);
+      launch_lb_refine(bx, cap, cand, ccount, h->L64, h->L32, ovf, novf, s);
+      int32_t n_ovf = 0;
+      e = hipGetLastError();
+      if (e == hipSuccess) e = hipMemcpyAsync(&n_ovf, novf, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e == hipSuccess && n_ovf > 0) {
+        launch_lb_overflow(bx, lb, ovf, n_ovf, h->L64, h->L32, s);
+        e = hipGetLastError();
+      }
+      std::vector<int32_t> cc(ix.n);
+      if (e == hipSuccess && ix.n > 0)
+        e = hipMemcpyAsync(cc.data(), ccount, ix.n * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      cleanup();
+      HIPTRY(e);
+      for (int32_t c : cc) h->cand_total += std::min(c, cap);
+      h->cand_ovf = n_ovf;
+    }
+    launch_blocks(ix, h->LB, h->bnorm, s);
+    HIPTRY(hipGetLastError());
+  }
+  HIPTRY(hipStreamSynchronize(s));
+  return RK_OK;
+}
+
+rk_status build_impl(const float* Q, int64_t n, const float* P, int64_t m, int32_t d,
+                     int32_t k_max, const rk_build_opts* opts_in, bool on_device, rk_index** out) {
+  if (!out) return fail(RK_E_INVAL, "out is NULL");
+  *out = nullptr;
+  rk_build_opts o;
+  rk_build_opts_default(&o);
+  if (opts_in) o = *opts_in;
+  rk_status st;
+  if ((st = check_sizes(n, m, d, k_max)) != RK_OK) return st;
+  if ((st = check_opts(o)) != RK_OK) return st;
+  if ((n > 0 && !Q) || (m > 0 && !P)) return fail(RK_E_INVAL, "Q or P is NULL");
+  if (!on_device) {
+    if (!host_values_ok(Q, n * d) || !host_values_ok(P, m * d))
+      return fail(RK_E_INVAL, "input has a non-finite value or |x| >= 2^40");
+  }
+  int ndev = 0;
+  HIPTRY(hipGetDeviceCount(&ndev));
+  if (o.device >= ndev) return fail(RK_E_INVAL, "device ordinal out of range");
+  auto t_start = std::chrono::steady_clock::now();
+
+  rk_index* h = new rk_index();
+  h->device = o.device;
+  h->opts = o;
+  auto bail = [&](rk_status s) { delete h; return s; };
+#define BTRY(expr)                                         \
+  do {                                                     \
+    hipError_t be_ = (expr);                               \
+    if (be_ != hipSuccess) {                               \
+      rk_status s_ = fail(be_ == hipErrorOutOfMemory ? RK_E_NOMEM : RK_E_DEVICE, \
+                          std::string(#expr) + ": " + hipGetErrorString(be_));   \
+      return bail(s_);                                     \
+    }                                                      \
+  } while (0)
+  BTRY(hipSetDevice(o.device));
+  BTRY(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+  hipStream_t s = h->stream;
+
+  DevIndex& ix = h->ix;
+  ix.n = n;
+  ix.m = m;
+  ix.n_pad = round_up(n, TILE);
+  ix.m_pad = round_up(m, TILE);
+  ix.d = d;
+  ix.d16 = (int32_t)round_up(d, 16);
+  ix.kmax = k_max;
+  ix.nB = (int32_t)(ix.n_pad / TILE);
+  ix.mB = (int32_t)(ix.m_pad / TILE);
+  const int64_t lb = (o.lb_items == 0 || o.lb_items >= m) ? m : o.lb_items;
+  ix.lb_items = (int32_t)lb;
+  ix.exact = (lb == m) ? 1 : 0;
+  ix.bf16 = o.precision == RK_BF16 ? 1 : 0;
+  h->eps32 = std::max(eps_fp32(d), o.margin_rel);
+  const double eps = std::max(ix.bf16 ? eps_bf16(d) : eps_fp32(d), o.margin_rel);
+  ix.eps_rel = f32_up(eps);
+  ix.eps_abs = std::ldexp((double)(d + 2), -124);
+  ix.cs_inflate = f32_up(1.0 + gamma_(d, 0x1p-53) + 8 * 0x1p-24);
+
+  // Raw inputs on the device (temporary when given host pointers).
+  const float *Qd = Q, *Pd = P;
+  float *Qtmp = nullptr, *Ptmp = nullptr;
+  int32_t* flag = nullptr;
+  std::vector<void*> tmp;
+  auto free_tmp = [&]() { for (void* p : tmp) (void)hipFree(p); tmp.clear(); };
+#define TTRY(expr)                                         \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) { free_tmp();  BTRY(e_); }       \
+  } while (0)
+  if (!on_device) {
+    if (n > 0) { TTRY(hipMalloc(&Qtmp, n * d * sizeof(float))); tmp.push_back(Qtmp); }
+    if (m > 0) { TTRY(hipMalloc(&Ptmp, m * d * sizeof(float))); tmp.push_back(Ptmp); }
+    if (n > 0) TTRY(hipMemcpyAsync(Qtmp, Q, n * d * sizeof(float), hipMemcpyHostToDevice, s));
+    if (m > 0) TTRY(hipMemcpyAsync(Ptmp, P, m * d * sizeof(float), hipMemcpyHostToDevice, s));
+    Qd = Qtmp;
+    Pd = Ptmp;
+  } else {
+    TTRY(hipMalloc(&flag, sizeof(int32_t)));
+    tmp.push_back(flag);
+    TTRY(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    launch_check_inputs(Qd, n * d, flag, s);
+    launch_check_inputs(Pd, m * d, flag, s);
+    int32_t bad = 0;
+    TTRY(hipMemcpyAsync(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TTRY(hipStreamSynchronize(s));
+    if (bad) { free_tmp(); return bail(fail(RK_E_INVAL, "input has a non-finite value or |x| >= 2^40")); }
+  }
+
+  // Step 1: squared norms, descending norm sort (stable by original index).
+  TTRY(h->dalloc(&h->s2Q, (size_t)n));
+  TTRY(h->dalloc(&h->s2P, (size_t)m));
+  launch_sqnorms(Qd, n, d, h->s2Q, s);
+  launch_sqnorms(Pd, m, d, h->s2P, s);
+  TTRY(hipGetLastError());
+  std::vector<double> k2Q(n), k2P(m);
+  if (n) TTRY(hipMemcpyAsync(k2Q.data(), h->s2Q, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (m) TTRY(hipMemcpyAsync(k2P.data(), h->s2P, m * sizeof(double), hipMemcpyDeviceToHost, s));
+  TTRY(hipStreamSynchronize(s));
+  auto sort_desc = [](const std::vector<double>& key) {
+    std::vector<int32_t> perm(key.size());
+    std::iota(perm.begin(), perm.end(), 0);
+    std::sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+      if (key[a] != key[b]) return key[a] > key[b];
+      return a < b;
+    });
+    return perm;
+  };
+  std::vector<int32_t> pQ = sort_desc(k2Q), pP = sort_desc(k2P);
+  TTRY(h->dalloc(&h->permQ, (size_t)n));
+  TTRY(h->dalloc(&h->permP, (size_t)m));
+  if (n) TTRY(hipMemcpyAsync(h->permQ, pQ.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (m) TTRY(hipMemcpyAsync(h->permP, pP.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));
+
+  // Sorted tiled copies and upward-rounded norms.
+  TTRY(h->dalloc(&h->Qt, (size_t)ix.n_pad * d));
+  TTRY(h->dalloc(&h->normQ, (size_t)ix.n_pad));
+  TTRY(h->dalloc(&h->Pt, (size_t)ix.m_pad * d));
+  TTRY(h->dalloc(&h->normP, (size_t)ix.m_pad));
+  TTRY(h->dalloc(&h->Prow, (size_t)m * d));
+  if (ix.bf16) {
+    TTRY(h->dalloc(&h->Qb, (size_t)ix.n_pad * ix.d16));
+    TTRY(h->dalloc(&h->Pb, (size_t)ix.m_pad * ix.d16));
+  }
+  launch_tile_rows(Qd, h->permQ, h->s2Q, n, ix.n_pad, d, ix.d16, h->Qt, h->normQ, h->Qb, nullptr, s);
+  launch_tile_rows(Pd, h->permP, h->s2P, m, ix.m_pad, d, ix.d16, h->Pt, h->normP, h->Pb, h->Prow, s);
+  TTRY(hipGetLastError());
+  TTRY(hipStreamSynchronize(s));
+  free_tmp();
+  ix.Qt = h->Qt; ix.Qb = h->Qb; ix.normQ = h->normQ; ix.permQ = h->permQ;
+  ix.Pt = h->Pt; ix.Pb = h->Pb; ix.Prow = h->Prow; ix.normP = h->normP;
+
+  // Steps 2-3: lower-bound arrays and blocks.
+  if ((st = build_bounds(h)) != RK_OK) return bail(st);
+
+  // Query workspace.
+  const int64_t W = (n + 31) / 32;
+  BTRY(h->dalloc(&h->ws.rbits, (size_t)std::max<int64_t>(W, 1)));
+  BTRY(h->dalloc(&h->ws.surv_idx, (size_t)ix.n_pad));
+  BTRY(h->dalloc(&h->ws.surv_s, (size_t)ix.n_pad));
+  BTRY(h->dalloc(&h->ws.rchk_idx, (size_t)ix.n_pad));
+  BTRY(h->dalloc(&h->ws.cnt, 4));
+  BTRY(h->dalloc(&h->ws.qnorm, 1));
+  BTRY(h->dalloc(&h->ctr_dev, 16));
+  BTRY(h->dalloc(&h->q_dev, (size_t)d));
+  BTRY(h->dalloc(&h->ids_dev, (size_t)std::max<int64_t>(n, 1)));
+  BTRY(h->dalloc(&h->count_dev, 1));
+  BTRY(hipMemsetAsync(h->ws.rbits, 0, std::max<int64_t>(W, 1) * sizeof(uint32_t), s));
+  BTRY(hipMemsetAsync(h->ws.cnt, 0, 4 * sizeof(int32_t), s));
+  BTRY(hipMemsetAsync(h->ctr_dev, 0, 16 * sizeof(unsigned long long), s));
+  h->ws.ctr = nullptr;
+  BTRY(hipHostMalloc((void**)&h->q_host, d * sizeof(float), hipHostMallocDefault));
+  h->hbufs.push_back(h->q_host);
+  BTRY(hipHostMalloc((void**)&h->ids_host, std::max<int64_t>(n, 1) * sizeof(int32_t), hipHostMallocMapped));
+  h->hbufs.push_back(h->ids_host);
+  BTRY(hipHostMalloc((void**)&h->count_host, sizeof(int64_t), hipHostMallocMapped));
+  h->hbufs.push_back(h->count_host);
+  BTRY(hipHostGetDevicePointer((void**)&h->ids_host_dev, h->ids_host, 0));
+  BTRY(hipHostGetDevicePointer((void**)&h->count_host_dev, h->count_host, 0));
+  BTRY(hipStreamSynchronize(s));
+  h->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  *out = h;
+  return RK_OK;
+#undef TTRY
+#undef BTRY
+}
+
+// Enqueue one query (device q) on stream s; ids/count are device-visible.
+// Ids go to ids[*base ...] when base is given (batch CSR), else ids[0 ...];
+// *out receives base + count.
+rk_status enqueue_query(rk_index* h, const float* q_dev, int32_t k, int32_t* ids, int64_t cap,
+                        const int64_t* base, int64_t* out, hipStream_t s, uint8_t* tcls,
+                        float* ts) {
+  const DevIndex& ix = h->ix;
+  if (k > ix.m || ix.n == 0) {
+    launch_fill_all(k > ix.m ? ix.n : 0, ids, cap, base, out, s);
+    HIPTRY(hipGetLastError());
+    h->queries++;
+    return RK_OK;
+  }
+  QueryWS ws = h->ws;
+  ws.ctr = h->counting ? h->ctr_dev : nullptr;
+  ws.trace_cls = tcls;
+  ws.trace_s = ts;
+  launch_filter(ix, q_dev, k, ws, s);
+  launch_verify(ix, q_dev, k, ws, s);
+  launch_recheck(ix, q_dev, k, ws, s);
+  launch_finalize(ix, ws, ids, cap, base, out, s);
+  HIPTRY(hipGetLastError());
+  h->queries++;
+  return RK_OK;
+}
+
+rk_status check_k(rk_index* h, int32_t k) {
+  if (k < 1) return fail(RK_E_INVAL, "k must be >= 1");
+  if (k > h->ix.kmax && k <= h->ix.m) {
+    if (!h->opts.auto_rebuild) return fail(RK_E_KMAX, "k > k_max (build with a larger k_max or set auto_rebuild)");
+    rk_status st = rk_index_rebuild(h, k);
+    if (st != RK_OK) return st;
+  }
+  return RK_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+void rk_build_opts_default(rk_build_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = RK_FP32;
+  o->lb_items = 0;
+  o->block_size = 0;
+  o->device = 0;
+  o->margin_rel = 0.0;
+  o->cand_cap = 0;
+  o->auto_rebuild = 0;
+}
+
+const char* rk_last_error(void) { return g_err.c_str(); }
+
+rk_status rk_build_index(const float* Q, int64_t n, const float* P, int64_t m, int32_t d,
+                         int32_t k_max, const rk_build_opts* opts, rk_index** out) {
+  return build_impl(Q, n, P, m, d, k_max, opts, false, out);
+}
+
+rk_status rk_build_index_dev(const float* Q, int64_t n, const float* P, int64_t m, int32_t d,
+                             int32_t k_max, const rk_build_opts* opts, rk_index** out) {
+  return build_impl(Q, n, P, m, d, k_max, opts, true, out);
+}
+
+void rk_index_free(rk_index* idx) { delete idx; }
+
+rk_status rk_index_rebuild(rk_index* h, int32_t k_max) {
+  if (!h) return fail(RK_E_INVAL, "index is NULL");
+  if (k_max < 1 || k_max > kMaxKmax) return fail(RK_E_INVAL, "k_max must be in [1, 128]");
+  HIPTRY(hipSetDevice(h->device));
+  auto t0 = std::chrono::steady_clock::now();
+  HIPTRY(hipStreamSynchronize(h->stream));
+  for (void* p : {(void*)h->L64, (void*)h->L32, (void*)h->LB, (void*)h->bnorm}) h->dfree(p);
+  h->footprint -= (size_t)h->ix.kmax * h->ix.n_pad * (sizeof(double) + sizeof(float)) +
+                  (size_t)h->ix.kmax * h->ix.nB * sizeof(float) + (size_t)std::max(h->ix.nB, 1) * sizeof(float);
+  h->ix.kmax = k_max;
+  rk_status st = build_bounds(h);
+  if (st != RK_OK) return st;
+  h->rebuilds++;
+  h->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return RK_OK;
+}
+
+rk_status rk_reverse_kmips(rk_index* h, const float* q, int32_t k, int32_t* ids, int64_t cap,
+                           int64_t* count) {
+  if (!h || !q || !count || (cap > 0 && !ids) || cap < 0) return fail(RK_E_INVAL, "NULL argument or cap < 0");
+  rk_status st = check_k(h, k);
+  if (st != RK_OK) return st;
+  if (!host_values_ok(q, h->ix.d)) return fail(RK_E_INVAL, "q has a non-finite value or |x| >= 2^40");
+  HIPTRY(hipSetDevice(h->device));
+  std::memcpy(h->q_host, q, h->ix.d * sizeof(float));
+  HIPTRY(hipMemcpyAsync(h->q_dev, h->q_host, h->ix.d * sizeof(float), hipMemcpyHostToDevice, h->stream));
+  st = enqueue_query(h, h->q_dev, k, h->ids_host_dev, std::max<int64_t>(h->ix.n, 1), nullptr,
+                     h->count_host_dev, h->stream, nullptr, nullptr);
+  if (st != RK_OK) return st;
+  HIPTRY(hipStreamSynchronize(h->stream));
+  const int64_t c = *(volatile int64_t*)h->count_host;
+  *count = c;
+  std::memcpy(ids, h->ids_host, std::min(c, cap) * sizeof(int32_t));
+  if (c > cap) return fail(RK_E_TRUNC, "result larger than cap");
+  return RK_OK;
+}
+
+rk_status rk_reverse_kmips_dev(rk_index* h, const float* q_dev, int32_t k, int32_t* ids_dev,
+                               int64_t cap, int64_t* count_dev, void* stream) {
+  if (!h || !q_dev || !count_dev || (cap > 0 && !ids_dev) || cap < 0) return fail(RK_E_INVAL, "NULL argument or cap < 0");
+  rk_status st = check_k(h, k);
+  if (st != RK_OK) return st;
+  HIPTRY(hipSetDevice(h->device));
+  hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+  return enqueue_query(h, q_dev, k, ids_dev, cap, nullptr, count_dev, s, nullptr, nullptr);
+}
+
+rk_status rk_reverse_kmips_trace(rk_index* h, const float* q, int32_t k, uint8_t* cls, float* shat) {
+  if (!h || !q || !cls) return fail(RK_E_INVAL, "NULL argument");
+  rk_status st = check_k(h, k);
+  if (st != RK_OK) return st;
+  if (!host_values_ok(q, h->ix.d)) return fail(RK_E_INVAL, "q has a non-finite value or |x| >= 2^40");
+  HIPTRY(hipSetDevice(h->device));
+  const int64_t n = h->ix.n;
+  uint8_t* tcls = nullptr;
+  float* ts = nullptr;
+  HIPTRY(hipMalloc(&tcls, std::max<int64_t>(n, 1)));
+  hipError_t e = hipMalloc(&ts, std::max<int64_t>(n, 1) * sizeof(float));
+  if (e != hipSuccess) { (void)hipFree(tcls); HIPTRY(e); }
+  auto done = [&](rk_status s_) { (void)hipFree(tcls); (void)hipFree(ts); return s_; };
+  hipStream_t s = h->stream;
+  if ((e = hipMemsetAsync(tcls, RK_C_BLOCK_NO, std::max<int64_t>(n, 1), s)) != hipSuccess ||
+      (e = hipMemsetAsync(ts, 0xFF, std::max<int64_t>(n, 1) * sizeof(float), s)) != hipSuccess ||
+      (e = hipMemcpyAsync(h->q_dev, q, h->ix.d * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess)
+    return done(fail(RK_E_DEVICE, hipGetErrorString(e)));
+  if (k > h->ix.m) {
+    std::memset(cls, RK_C_LEMMA2_YES, n);
+    if (shat) for (int64_t i = 0; i < n; ++i) shat[i] = NAN;
+    return done(RK_OK);
+  }
+  st = enqueue_query(h, h->q_dev, k, h->ids_dev, n, nullptr, h->count_dev, s, tcls, ts);
+  if (st != RK_OK) return done(st);
+  if ((e = hipMemcpyAsync(cls, tcls, n, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (shat && (e = hipMemcpyAsync(shat, ts, n * sizeof(float), hipMemcpyDeviceToHost, s)) != hipSuccess) ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return done(fail(RK_E_DEVICE, hipGetErrorString(e)));
+  return done(RK_OK);
+}
+
+static rk_status check_batch_ks(rk_index* h, const int32_t* ks, int64_t nq) {
+  int32_t need = 0;
+  for (int64_t i = 0; i < nq; ++i) {
+    if (ks[i] < 1) return fail(RK_E_INVAL, "k must be >= 1");
+    if (ks[i] > h->ix.kmax && ks[i] <= h->ix.m) need = std::max(need, ks[i]);
+  }
+  if (need) {
+    if (!h->opts.auto_rebuild) return fail(RK_E_KMAX, "k > k_max (build with a larger k_max or set auto_rebuild)");
+    return rk_index_rebuild(h, need);
+  }
+  return RK_OK;
+}
+
+rk_status rk_reverse_kmips_batch_dev(rk_index* h, const float* qs_dev, int64_t nq,
+                                     const int32_t* ks, int64_t* offsets_dev, int32_t* ids_dev,
+                                     int64_t cap, void* stream) {
+  if (!h || nq < 0 || (nq > 0 && (!qs_dev || !ks)) || !offsets_dev || cap < 0 || (cap > 0 && !ids_dev))
+    return fail(RK_E_INVAL, "NULL argument or negative size");
+  rk_status st = check_batch_ks(h, ks, nq);
+  if (st != RK_OK) return st;
+  HIPTRY(hipSetDevice(h->device));
+  hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+  launch_set_i64(offsets_dev, 0, s);
+  HIPTRY(hipGetLastError());
+  for (int64_t i = 0; i < nq; ++i) {
+    st = enqueue_query(h, qs_dev + i * h->ix.d, ks[i], ids_dev, cap, offsets_dev + i,
+                       offsets_dev + i + 1, s, nullptr, nullptr);
+    if (st != RK_OK) return st;
+  }
+  return RK_OK;
+}
+
+rk_status rk_reverse_kmips_batch(rk_index* h, const float* qs, int64_t nq, const int32_t* ks,
+                                 int64_t* offsets, int32_t* ids, int64_t cap) {
+  if (!h || nq < 0 || (nq > 0 && (!qs || !ks)) || !offsets || cap < 0 || (cap > 0 && !ids))
+    return fail(RK_E_INVAL, "NULL argument or negative size");
+  rk_status st = check_batch_ks(h, ks, nq);
+  if (st != RK_OK) return st;
+  if (!host_values_ok(qs, nq * h->ix.d)) return fail(RK_E_INVAL, "a query has a non-finite value or |x| >= 2^40");
+  HIPTRY(hipSetDevice(h->device));
+  hipStream_t s = h->stream;
+  float* qd = nullptr;
+  int64_t* od = nullptr;
+  int32_t* idd = nullptr;
+  const int64_t dcap = std::max<int64_t>(cap, 1);
+  std::vector<void*> tmp;
+  auto done = [&](rk_status r) { (void)hipStreamSynchronize(s); for (void* p : tmp) (void)hipFree(p); return r; };
+  hipError_t e = hipMalloc(&qd, std::max<int64_t>(nq * h->ix.d, 1) * sizeof(float));
+  if (e == hipSuccess) { tmp.push_back(qd); e = hipMalloc(&od, (nq + 1) * sizeof(int64_t)); }
+  if (e == hipSuccess) { tmp.push_back(od); e = hipMalloc(&idd, dcap * sizeof(int32_t)); }
+  if (e == hipSuccess) { tmp.push_back(idd); if (nq) e = hipMemcpyAsync(qd, qs, nq * h->ix.d * sizeof(float), hipMemcpyHostToDevice, s); }
+  if (e != hipSuccess) return done(fail(e == hipErrorOutOfMemory ? RK_E_NOMEM : RK_E_DEVICE, hipGetErrorString(e)));
+  st = rk_reverse_kmips_batch_dev(h, qd, nq, ks, od, idd, cap, s);
+  if (st != RK_OK) return done(st);
+  if ((e = hipMemcpyAsync(offsets, od, (nq + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return done(fail(RK_E_DEVICE, hipGetErrorString(e)));
+  const int64_t total = offsets[nq];
+  const int64_t ncopy = std::min(total, cap);
+  if (ncopy > 0 && (e = hipMemcpyAsync(ids, idd, ncopy * sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return done(fail(RK_E_DEVICE, hipGetErrorString(e)));
+  st = done(RK_OK);
+  if (total > cap) return fail(RK_E_TRUNC, "results larger than cap");
+  return st;
+}
+
+rk_status rk_index_set_counting(rk_index* h, int32_t on) {
+  if (!h) return fail(RK_E_INVAL, "index is NULL");
+  h->counting = on != 0;
+  return RK_OK;
+}
+
+rk_status rk_index_reset_counters(rk_index* h) {
+  if (!h) return fail(RK_E_INVAL, "index is NULL");
+  HIPTRY(hipSetDevice(h->device));
+  HIPTRY(hipMemsetAsync(h->ctr_dev, 0, 16 * sizeof(unsigned long long), h->stream));
+  HIPTRY(hipStreamSynchronize(h->stream));
+  h->queries = 0;
+  return RK_OK;
+}
+
+rk_status rk_index_stats(const rk_index* hc, rk_stats* o) {
+  if (!hc || !o) return fail(RK_E_INVAL, "NULL argument");
+  rk_index* h = const_cast<rk_index*>(hc);
+  std::memset(o, 0, sizeof(*o));
+  const DevIndex& ix = h->ix;
+  o->n = ix.n; o->m = ix.m; o->d = ix.d; o->k_max = ix.kmax; o->lb_items = ix.lb_items;
+  o->block_size = TILE; o->n_blocks = ix.nB; o->precision = ix.bf16 ? RK_BF16 : RK_FP32;
+  o->footprint_bytes = (int64_t)h->footprint;
+  o->build_ms = h->build_ms;
+  o->build_cand_total = h->cand_total;
+  o->build_cand_overflow_users = h->cand_ovf;
+  o->rebuilds = h->rebuilds;
+  o->queries = h->queries;
+  unsigned long long c[16] = {};
+  HIPTRY(hipSetDevice(h->device));
+  HIPTRY(hipMemcpyAsync(c, h->ctr_dev, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+  HIPTRY(hipStreamSynchronize(h->stream));
+  o->blocks_visited = c[C_BLOCKS]; o->blocks_pruned = c[C_PRUNED]; o->users_evaluated = c[C_USERS];
+  o->lemma1_no = c[C_L1NO]; o->lemma2_yes = c[C_L2YES]; o->table_yes = c[C_TYES];
+  o->survivors = c[C_SURV]; o->scan_items = c[C_SCAN]; o->rechecks = c[C_RCHK]; o->results = c[C_RES];
+  return RK_OK;
+}
+
+rk_status rk_index_export(const rk_index* hc, int32_t field, void* dst, int64_t bytes) {
+  if (!hc || !dst) return fail(RK_E_INVAL, "NULL argument");
+  rk_index* h = const_cast<rk_index*>(hc);
+  const DevIndex& ix = h->ix;
+  const void* src = nullptr;
+  int64_t need = 0, rows = 0, width = 0, pitch = 0;  // 2-D copies drop padding
+  switch (field) {
+    case RK_F_PERM_Q: src = h->permQ; need = ix.n * 4; break;
+    case RK_F_PERM_P: src = h->permP; need = ix.m * 4; break;
+    case RK_F_SQNORM_Q: src = h->s2Q; need = ix.n * 8; break;
+    case RK_F_SQNORM_P: src = h->s2P; need = ix.m * 8; break;
+    case RK_F_NORM_Q: src = h->normQ; need = ix.n * 4; break;
+    case RK_F_NORM_P: src = h->normP; need = ix.m * 4; break;
+    case RK_F_L64: src = h->L64; rows = ix.kmax; width = ix.n * 8; pitch = ix.n_pad * 8; break;
+    case RK_F_L32: src = h->L32; rows = ix.kmax; width = ix.n * 4; pitch = ix.n_pad * 4; break;
+    case RK_F_LB: src = h->LB; need = (int64_t)ix.kmax * ix.nB * 4; break;
+    case RK_F_BNORM: src = h->bnorm; need = (int64_t)ix.nB * 4; break;
+    default: return fail(RK_E_INVAL, "unknown field");
+  }
+  if (rows) need = rows * width;
+  if (bytes != need) return fail(RK_E_INVAL, "size mismatch for field");
+  if (need == 0) return RK_OK;
+  HIPTRY(hipSetDevice(h->device));
+  if (rows) {
+    HIPTRY(hipMemcpy2DAsync(dst, width, src, pitch, width, rows, hipMemcpyDeviceToHost, h->stream));
+  } else {
+    HIPTRY(hipMemcpyAsync(dst, src, need, hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPTRY(hipStreamSynchronize(h->stream));
+  return RK_OK;
+}
+
+int64_t rk_index_footprint(int64_t n, int64_t m, int32_t d, int32_t k_max, const rk_build_opts* opts) {
+  rk_build_opts o;
+  rk_build_opts_default(&o);
+  if (opts) o = *opts;
+  if (n < 0 || m < 0 || d < 1 || k_max < 1) return -1;
+  const int64_t np = round_up(n, TILE), mp = round_up(m, TILE), nB = np / TILE;
+  const int64_t d16 = round_up(d, 16);
+  int64_t b = 0;
+  b += n * 8 + m * 8 + n * 4 + m * 4;                 // squared norms, permutations
+  b += np * d * 4 + np * 4 + mp * d * 4 + mp * 4 + m * d * 4;  // tiled copies, norms, rows
+  if (o.precision == RK_BF16) b += (np + mp) * d16 * 2;
+  b += (int64_t)k_max * np * 12 + (int64_t)k_max * nB * 4 + nB * 4;  // L64, L32, LB, bnorm
+  b += ((n + 31) / 32) * 4 + np * 12 + 4 * 4 + 4 + 16 * 8 + d * 4 + std::max<int64_t>(n, 1) * 4 + 8;
+  return b;
+}
+
+}  // extern "C"
