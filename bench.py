@@ -1,0 +1,216 @@
+"""Benchmark: exact reverse k-MIPS queries/sec on one MI355X.
+
+Workload (default): 100,000 users x 20,000 items, d = 50, log-normal norms
+(sigma 0.5), k_max = 25; 1,000 query items drawn from P, each evaluated at
+k = 1, 5, 10 and 25 (4,000 queries).  The index is built once (offline,
+reported as build_ms, not part of the timed region).  A step is one pass of
+the whole online path over all 4,000 queries, with queries, k values and
+outputs resident on the device, results in CSR form in device memory.
+
+Prints one JSON line.  Also reports: per-query latency (p50/p99) of the
+one-query host API, the dominant kernel's roofline fraction from per-kernel
+HIP events in the same run, and the CPU oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="plain")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--lb-items", type=int, default=0,
+                    help="|P'| of the lower-bound arrays; 0 = all items (exact table)")
+    ap.add_argument("--latency-queries", type=int, default=1000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-latency", action="store_true")
+    return ap.parse_args()
+
+
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+KERNEL_NAMES = {"filter": "k_filter", "batch_filter": "k_bfilter", "batch_pairs": "k_brecheck_exact/k_bverify",
+                "batch_assemble": "k_bscan+k_bassemble", "batch_prep": "k_bnorms+k_bsort+k_btile",
+                "recheck": "k_recheck", "finalize": "k_finalize", "verify": "k_verify"}
+
+
+def dominant_roofline(cls: str, times, st: dict, d: int, precision: str) -> dict:
+    """Roofline entry of the dominant kernel class from its event-timed
+    launches and the per-step counters.
+
+    batch_filter (MFMA): algorithmic flops = 2*d (unpadded) per evaluated
+    (user, query) pair, i.e. pairs in blocks Lemma 3 did not prune.
+    filter (one query, HBM): bytes = 8 per visited block + 64 users x (row +
+    norm + bound) per evaluated block."""
+    ms, launches = times
+    avg_s = ms / 1e3 / max(launches, 1)
+    if cls == "batch_filter":
+        flops = 2.0 * d * st["users_evaluated"] / max(launches, 1)
+        ach = flops / avg_s / 1e12
+        peak = MFMA_PEAK_TFLOPS[precision]
+        return {"bound": "mfma", "kernel": KERNEL_NAMES[cls], "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "avg_launch_us": avg_s * 1e6,
+                "launches_per_step": launches, "algorithmic_flops_per_launch": flops,
+                "traffic": None}
+    elem = 2 if precision == "bf16" else 4
+    evaluated_blocks = st["blocks_visited"] - st["blocks_pruned"]
+    nbytes = (8.0 * st["blocks_visited"] + evaluated_blocks * 64.0 * (d * elem + 8)) / max(launches, 1)
+    ach = nbytes / avg_s / 1e9
+    return {"bound": "hbm", "kernel": KERNEL_NAMES.get(cls, cls), "achieved": ach,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "avg_launch_us": avg_s * 1e6, "launches_per_step": launches,
+            "algorithmic_bytes_per_launch": nbytes, "traffic": None}
+
+
+def cpu_baseline(w, ks, budget_s: float) -> dict:
+    import oracle
+    threads = oracle.num_threads()
+    done, t0 = 0, time.perf_counter()
+    qs = w.queries
+    while done < len(ks):
+        oracle.brute(w.Q, w.P, qs[done], int(ks[done]))
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"brute-force definition (float64) on the first {done} of the "
+                      f"{len(ks)} (q,k) queries of the same workload, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has "
+              f"no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2110_07131_amd import datagen
+    from paper_2110_07131_amd.rkmips import Index
+
+    assert torch.cuda.is_available(), "no HIP device"
+    torch.cuda.set_device(0)
+    cfg = datagen.CONFIGS[args.config]
+    w = datagen.config_workload(args.config)
+    n, m, d, kmax = cfg["n"], cfg["m"], cfg["d"], cfg["k_max"]
+    qs_np, ks = w.queries, w.ks.astype(np.int32)
+    nq = len(ks)
+    print(f"[bench] workload {args.config}: n={n} m={m} d={d} k_max={kmax} queries={nq}",
+          file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    idx = Index.build(w.Q, w.P, kmax, precision=args.precision, lb_items=args.lb_items)
+    build_s = time.perf_counter() - t0
+    st0 = idx.stats()
+    print(f"[bench] index built in {build_s:.2f} s", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    qs = torch.from_numpy(qs_np).to(dev)
+    cap = max(1, nq * 256)
+    offsets = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+    ids = torch.empty(cap, dtype=torch.int32, device=dev)
+    torch_stream = torch.cuda.Stream()  # default priority
+    torch.cuda.set_stream(torch_stream)
+    stream = torch_stream.cuda_stream
+
+    def step():
+        idx.reverse_kmips_batch_dev(qs, ks, offsets, ids, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    qps = nq * args.steps / elapsed
+    total = int(offsets[-1].item())
+    print(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step, {qps:.0f} queries/s, "
+          f"{total} result ids per step", file=sys.stderr, flush=True)
+    if total > cap:
+        raise RuntimeError("result capacity exceeded")
+
+    # Sampled exactness check of the timed output against the host API.
+    off_h = offsets.cpu().numpy()
+    ids_h = ids[:total].cpu().numpy()
+    for i in np.linspace(0, nq - 1, 8).astype(int):
+        ref = idx.reverse_kmips(qs_np[i], int(ks[i]))
+        assert np.array_equal(ids_h[off_h[i]:off_h[i + 1]], ref), f"batch/single mismatch at {i}"
+
+    # Dominant kernel: per-kernel HIP events over one more pass, and the
+    # algorithmic work from the counters of one counted pass.
+    idx.set_counting(True)
+    idx.reset_counters()
+    step()
+    torch.cuda.synchronize()
+    st = idx.stats()
+    idx.set_counting(False)
+    idx.set_timing(8 * nq + 64)
+    step()
+    torch.cuda.synchronize()
+    kt = idx.kernel_times()
+    idx.set_timing(0)
+    dom = max(kt, key=lambda c: kt[c][0])
+    roofline = dominant_roofline(dom, kt[dom], st, d, args.precision)
+    kernel_share = {c: {"ms_per_step": v[0], "launches": v[1]} for c, v in kt.items()}
+
+    lat = None
+    if not args.no_latency:
+        nl = min(args.latency_queries, nq)
+        times = []
+        for i in range(nl):
+            t = time.perf_counter()
+            idx.reverse_kmips(qs_np[i], int(ks[i]))
+            times.append(time.perf_counter() - t)
+        times = np.array(times) * 1e3
+        lat = {"p50_ms": float(np.percentile(times, 50)), "p99_ms": float(np.percentile(times, 99)),
+               "qps": nl / (times.sum() / 1e3), "queries": nl,
+               "what": "one query at a time through the host API (H2D of q, ids on host)"}
+
+    cpu = None if args.no_cpu else cpu_baseline(w, ks, args.cpu_seconds)
+
+    line = {
+        "metric": "reverse k-MIPS queries/sec (exact sets) and p50/p99 latency at 1 MI355X",
+        "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision.replace("fp", "f"),
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: |Q|={n} |P|={m} d={d} k_max={kmax} "
+                               f"lognormal-norm Gaussian vectors, seed 0, {nq // len(set(ks.tolist())) if args.config == 'plain' else nq} "
+                               f"query items from P x k in {sorted(set(ks.tolist())) if len(set(ks.tolist())) < 8 else '1..' + str(kmax)}",
+                   "queries_per_step": nq, "lb_items": args.lb_items or m,
+                   "precision": args.precision, "form": "device-resident batch, CSR output"},
+        "p50_ms": lat["p50_ms"] if lat else None, "p99_ms": lat["p99_ms"] if lat else None,
+        "latency": lat,
+        "roofline": roofline,
+        "dominant_kernel_class": dom,
+        "kernel_time_per_step": kernel_share,
+        "counters_per_step": {k: st[k] for k in ("blocks_visited", "blocks_pruned", "users_evaluated",
+                                                 "lemma1_no", "lemma2_yes", "table_yes", "survivors",
+                                                 "scan_items", "rechecks", "results")},
+        "build_ms": st0["build_ms"], "index_bytes": st0["footprint_bytes"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -75,7 +75,11 @@ typedef struct {
     int32_t auto_rebuild; /* nonzero: a query with k > k_max first rebuilds
                              the lower-bound arrays with k_max = k (the
                              paper's rule for k > k_max, Section 4.1) */
-    int32_t reserved[6];
+    int32_t pair_cap;     /* 0 = default.  Capacity of the batched path's list
+                             of undecided (user, query) pairs per chunk; pairs
+                             beyond it are decided in float64 inside the
+                             filter kernel (a test hook for that path) */
+    int32_t reserved[5];
 } rk_build_opts;
 
 /* Counters and sizes of an index.  Query counters accumulate over every
@@ -181,6 +185,18 @@ rk_status rk_reverse_kmips_batch_dev(rk_index *idx, const float *qs_dev,
  * computed).  shat may be NULL.  Host buffers.  Synchronous. */
 rk_status rk_reverse_kmips_trace(rk_index *idx, const float *q, int32_t k,
                                  uint8_t *cls, float *shat);
+
+/* Per-kernel event timing for profiling: with max_launches > 0 every
+ * kernel the index launches afterwards is bracketed by two HIP events on the
+ * stream it runs on (up to max_launches launches; later ones untimed).
+ * rk_index_kernel_times waits for them and returns, per kernel class
+ * (0 filter, 1 verify, 2 recheck, 3 finalize, 4 fill-all, 5 batch
+ * preparation, 6 batch filter, 7 batch pair decisions, 8 batch assembly),
+ * the summed milliseconds and launch counts, then clears the record.
+ * 0 turns timing off. */
+rk_status rk_index_set_timing(rk_index *idx, int32_t max_launches);
+rk_status rk_index_kernel_times(rk_index *idx, double *ms, int64_t *launches,
+                                int32_t nclass);
 
 /* Counters are off by default (they cost atomics on the query path). */
 rk_status rk_index_set_counting(rk_index *idx, int32_t on);

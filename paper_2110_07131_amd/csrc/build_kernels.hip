@@ -277,6 +277,9 @@ void launch_lb_candidates(const DevIndex& ix, int64_t S_end, const float* t0, in
                           int32_t* cand, int32_t* ccount, hipStream_t s) {
   if (ix.nB == 0) return;
   size_t lds = (size_t)ix.d * TILE * sizeof(float) + TILE * sizeof(int32_t);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_lb_candidates,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_lb_candidates, dim3(ix.nB), dim3(256), lds, s, ix, S_end, t0, cap, cand,
                      ccount);
 }

@@ -1,0 +1,40 @@
+// Batched query path: device workspace view and launch wrappers.
+#pragma once
+#include "rk_common.h"
+
+namespace rk {
+
+constexpr int kBatchChunkMax = 4096;  // queries per chunk (single-workgroup sort in LDS)
+
+struct BatchView {
+  const float* qs;              // chunk queries [nq][d], caller order
+  float* qn;                    // [nq] |q| rounded up, caller order
+  int32_t* perm;                // [nq] sorted position -> caller-order index
+  float* qt;                    // sorted query tiles, fp32 [T][d][64]
+  uint16_t* qb;                 // sorted query tiles, bf16 [T][G][64][8]
+  float* qn_s;                  // [nq_pad] sorted norms
+  int32_t* k_s;                 // [nq_pad] sorted k (0 = padding or no work)
+  int32_t nq_pad;
+  uint32_t* bits;               // [nq][W] result bits by original user id
+  int64_t W;                    // words per bitmap row
+  unsigned long long* counts;   // [nq] result sizes, caller order
+  uint8_t* all;                 // [nq] 1 if k > m (every user is a member)
+  int64_t n;                    // users
+  int32_t* npairs;              // undecided pairs appended (may exceed cap)
+  int32_t pair_cap;
+  int32_t* pair_u;              // sorted user index
+  int32_t* pair_j;              // sorted query position
+  float* pair_s;                // bulk-precision u.q
+  unsigned long long* ctr;      // statistics or nullptr
+};
+
+void launch_bprep(const DevIndex& ix, const BatchView& bv, const int32_t* ks_dev, int32_t nq,
+                  hipStream_t s);
+size_t bfilter_lds_bytes(const DevIndex& ix);
+void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s);
+void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s);
+// offs[0] must hold the chunk's first offset; writes offs[1..nq] and ids.
+void launch_bassemble(const BatchView& bv, int32_t nq, const int64_t* base, int64_t* offs,
+                      int32_t* ids, int64_t cap, hipStream_t s);
+
+}  // namespace rk

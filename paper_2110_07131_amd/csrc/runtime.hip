@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "rk_batch.h"
 #include "rk_kernels.h"
 
 using namespace rk;
@@ -59,7 +60,7 @@ struct rk_index {
   rk_build_opts opts{};
   DevIndex ix{};
   double eps32 = 0;  // float32 bound (build candidate pass)
-  std::vector<void*> dbufs;
+  std::vector<std::pair<void*, size_t>> dbufs;  // owned device buffers and sizes
   std::vector<void*> hbufs;
   size_t footprint = 0;
   // owned device arrays
@@ -75,12 +76,32 @@ struct rk_index {
   int64_t* count_dev = nullptr;
   unsigned long long* ctr_dev = nullptr;
   bool counting = false;
+  // optional per-kernel event timing (kernel class, start, end)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+  size_t ev_next = 0;
   // pinned host staging (ids/count are mapped: the finalize kernel writes them)
   float* q_host = nullptr;
   int32_t* ids_host = nullptr;
   int64_t* count_host = nullptr;
   int32_t* ids_host_dev = nullptr;
   int64_t* count_host_dev = nullptr;
+  // batched-query workspace (grown on demand)
+  struct {
+    int32_t qcap = 0;       // queries per chunk it is sized for
+    int64_t pair_cap = 0;
+    float *qn = nullptr, *qt = nullptr, *qn_s = nullptr, *pair_s = nullptr;
+    uint16_t* qb = nullptr;
+    int32_t *perm = nullptr, *k_s = nullptr, *npairs = nullptr, *pair_u = nullptr,
+            *pair_j = nullptr, *ks_dev = nullptr;
+    uint32_t* bits = nullptr;
+    unsigned long long* counts = nullptr;
+    uint8_t* all = nullptr;
+    int32_t* ks_pinned = nullptr;   // host staging of k values
+    int64_t ks_pinned_cap = 0;
+    hipEvent_t ks_done = nullptr;   // the last copy out of ks_pinned
+  } bw;
   // build statistics
   double build_ms = 0;
   int64_t cand_total = 0, cand_ovf = 0, rebuilds = 0;
@@ -89,7 +110,9 @@ struct rk_index {
   ~rk_index() {
     if (device >= 0) (void)hipSetDevice(device);
     if (stream) (void)hipStreamSynchronize(stream);
-    for (void* p : dbufs) (void)hipFree(p);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (bw.ks_done) (void)hipEventDestroy(bw.ks_done);
+    for (auto& b : dbufs) (void)hipFree(b.first);
     for (void* p : hbufs) (void)hipHostFree(p);
     if (stream) (void)hipStreamDestroy(stream);
   }
@@ -100,17 +123,19 @@ struct rk_index {
     if (count == 0) count = 1;
     hipError_t e = hipMalloc((void**)p, count * sizeof(T));
     if (e == hipSuccess) {
-      dbufs.push_back(*p);
+      dbufs.push_back({(void*)*p, count * sizeof(T)});
       footprint += count * sizeof(T);
     }
     return e;
   }
   void dfree(void* p) {
-    auto it = std::find(dbufs.begin(), dbufs.end(), p);
-    if (it != dbufs.end()) {
-      dbufs.erase(it);
-      (void)hipFree(p);
-    }
+    for (auto it = dbufs.begin(); it != dbufs.end(); ++it)
+      if (it->first == p) {
+        footprint -= it->second;
+        (void)hipFree(p);
+        dbufs.erase(it);
+        return;
+      }
   }
 };
 
@@ -123,6 +148,7 @@ rk_status check_opts(const rk_build_opts& o) {
   if (!(o.margin_rel >= 0.0) || !std::isfinite(o.margin_rel) || o.margin_rel >= 0.5)
     return fail(RK_E_INVAL, "margin_rel must be finite, >= 0 and < 0.5");
   if (o.cand_cap < 0) return fail(RK_E_INVAL, "cand_cap must be >= 0");
+  if (o.pair_cap < 0) return fail(RK_E_INVAL, "pair_cap must be >= 0");
   if (o.device < 0) return fail(RK_E_INVAL, "device must be >= 0");
   return RK_OK;
 }
@@ -371,6 +397,31 @@ rk_status build_impl(const float* Q, int64_t n, const float* P, int64_t m, int32
 }
 
 // Enqueue one query (device q) on stream s; ids/count are device-visible.
+// Kernel classes of the per-kernel event timing.
+enum KClass {
+  K_FILTER = 0, K_VERIFY, K_RECHECK, K_FINALIZE, K_FILL,
+  K_BPREP, K_BFILTER, K_BPAIRS, K_BASSEMBLE, K_NCLASS
+};
+
+// Records an event before a launch when timing is on; returns the pool slot.
+struct Timer {
+  rk_index* h;
+  hipStream_t s;
+  int cls;
+  hipEvent_t e0 = nullptr;
+  Timer(rk_index* h_, hipStream_t s_, int c) : h(h_), s(s_), cls(c) {
+    if (!h->timing || h->ev_next + 2 > h->ev_pool.size()) return;
+    e0 = h->ev_pool[h->ev_next++];
+    (void)hipEventRecord(e0, s);
+  }
+  ~Timer() {
+    if (!e0) return;
+    hipEvent_t e1 = h->ev_pool[h->ev_next++];
+    (void)hipEventRecord(e1, s);
+    h->ev_used.push_back({cls, {e0, e1}});
+  }
+};
+
 // Ids go to ids[*base ...] when base is given (batch CSR), else ids[0 ...];
 // *out receives base + count.
 rk_status enqueue_query(rk_index* h, const float* q_dev, int32_t k, int32_t* ids, int64_t cap,
@@ -378,6 +429,7 @@ rk_status enqueue_query(rk_index* h, const float* q_dev, int32_t k, int32_t* ids
                         float* ts) {
   const DevIndex& ix = h->ix;
   if (k > ix.m || ix.n == 0) {
+    Timer t(h, s, K_FILL);
     launch_fill_all(k > ix.m ? ix.n : 0, ids, cap, base, out, s);
     HIPTRY(hipGetLastError());
     h->queries++;
@@ -387,10 +439,10 @@ rk_status enqueue_query(rk_index* h, const float* q_dev, int32_t k, int32_t* ids
   ws.ctr = h->counting ? h->ctr_dev : nullptr;
   ws.trace_cls = tcls;
   ws.trace_s = ts;
-  launch_filter(ix, q_dev, k, ws, s);
-  launch_verify(ix, q_dev, k, ws, s);
-  launch_recheck(ix, q_dev, k, ws, s);
-  launch_finalize(ix, ws, ids, cap, base, out, s);
+  { Timer t(h, s, K_FILTER); launch_filter(ix, q_dev, k, ws, s); }
+  if (!ix.exact) { Timer t(h, s, K_VERIFY); launch_verify(ix, q_dev, k, ws, s); }
+  { Timer t(h, s, K_RECHECK); launch_recheck(ix, q_dev, k, ws, s); }
+  { Timer t(h, s, K_FINALIZE); launch_finalize(ix, ws, ids, cap, base, out, s); }
   HIPTRY(hipGetLastError());
   h->queries++;
   return RK_OK;
@@ -402,6 +454,123 @@ rk_status check_k(rk_index* h, int32_t k) {
     if (!h->opts.auto_rebuild) return fail(RK_E_KMAX, "k > k_max (build with a larger k_max or set auto_rebuild)");
     rk_status st = rk_index_rebuild(h, k);
     if (st != RK_OK) return st;
+  }
+  return RK_OK;
+}
+
+rk_status check_batch_ks(rk_index* h, const int32_t* ks, int64_t nq) {
+  int32_t need = 0;
+  for (int64_t i = 0; i < nq; ++i) {
+    if (ks[i] < 1) return fail(RK_E_INVAL, "k must be >= 1");
+    if (ks[i] > h->ix.kmax && ks[i] <= h->ix.m) need = std::max(need, ks[i]);
+  }
+  if (need) {
+    if (!h->opts.auto_rebuild) return fail(RK_E_KMAX, "k > k_max (build with a larger k_max or set auto_rebuild)");
+    return rk_index_rebuild(h, need);
+  }
+  return RK_OK;
+}
+
+constexpr int64_t kBitmapBudget = 512ll << 20;  // bytes of per-query result bits per chunk
+constexpr int64_t kPairBudget = 1ll << 26;       // undecided-pair list entries per chunk
+constexpr size_t kMaxLds = 160 * 1024;
+
+rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
+  auto& b = h->bw;
+  if (b.qcap >= chunk) return RK_OK;
+  HIPTRY(hipStreamSynchronize(h->stream));
+  for (void* p : {(void*)b.qn, (void*)b.qt, (void*)b.qn_s, (void*)b.pair_s, (void*)b.qb,
+                  (void*)b.perm, (void*)b.k_s, (void*)b.npairs, (void*)b.pair_u, (void*)b.pair_j,
+                  (void*)b.ks_dev, (void*)b.bits, (void*)b.counts, (void*)b.all})
+    if (p) h->dfree(p);
+  const DevIndex& ix = h->ix;
+  const int64_t cp = round_up(chunk, TILE), W = (ix.n + 31) / 32;
+  int64_t pc = std::min<int64_t>((int64_t)chunk * std::max<int64_t>(ix.n_pad, 1), kPairBudget);
+  if (h->opts.pair_cap > 0) pc = h->opts.pair_cap;
+  b.qcap = 0;
+  HIPTRY(h->dalloc(&b.qn, chunk));
+  HIPTRY(h->dalloc(&b.perm, chunk));
+  HIPTRY(h->dalloc(&b.qt, cp * ix.d));
+  if (ix.bf16) HIPTRY(h->dalloc(&b.qb, cp * ix.d16));
+  HIPTRY(h->dalloc(&b.qn_s, cp));
+  HIPTRY(h->dalloc(&b.k_s, cp));
+  HIPTRY(h->dalloc(&b.bits, (size_t)chunk * std::max<int64_t>(W, 1)));
+  HIPTRY(h->dalloc(&b.counts, chunk));
+  HIPTRY(h->dalloc(&b.all, chunk));
+  HIPTRY(h->dalloc(&b.npairs, 1));
+  HIPTRY(h->dalloc(&b.pair_u, pc));
+  HIPTRY(h->dalloc(&b.pair_j, pc));
+  HIPTRY(h->dalloc(&b.pair_s, pc));
+  HIPTRY(h->dalloc(&b.ks_dev, chunk));
+  HIPTRY(hipMemsetAsync(b.bits, 0, (size_t)chunk * std::max<int64_t>(W, 1) * 4, h->stream));
+  HIPTRY(hipMemsetAsync(b.counts, 0, (size_t)chunk * 8, h->stream));
+  HIPTRY(hipStreamSynchronize(h->stream));
+  b.qcap = chunk;
+  b.pair_cap = pc;
+  return RK_OK;
+}
+
+// Stage k values in pinned memory (guarded by an event so a previous copy
+// out of it has finished) and copy them to the device.
+rk_status stage_ks(rk_index* h, const int32_t* ks, int64_t nq, int32_t* dst, hipStream_t s) {
+  auto& b = h->bw;
+  if (!b.ks_done) HIPTRY(hipEventCreateWithFlags(&b.ks_done, hipEventDisableTiming));
+  HIPTRY(hipEventSynchronize(b.ks_done));
+  if (b.ks_pinned_cap < nq) {
+    if (b.ks_pinned) {
+      (void)hipHostFree(b.ks_pinned);
+      h->hbufs.erase(std::find(h->hbufs.begin(), h->hbufs.end(), (void*)b.ks_pinned));
+    }
+    b.ks_pinned = nullptr;
+    b.ks_pinned_cap = 0;
+    HIPTRY(hipHostMalloc((void**)&b.ks_pinned, nq * sizeof(int32_t), hipHostMallocDefault));
+    h->hbufs.push_back(b.ks_pinned);
+    b.ks_pinned_cap = nq;
+  }
+  std::memcpy(b.ks_pinned, ks, nq * sizeof(int32_t));
+  HIPTRY(hipMemcpyAsync(dst, b.ks_pinned, nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPTRY(hipEventRecord(b.ks_done, s));
+  return RK_OK;
+}
+
+rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int32_t* ks,
+                        int64_t* offs, int32_t* ids, int64_t cap, hipStream_t s) {
+  const DevIndex& ix = h->ix;
+  launch_set_i64(offs, 0, s);
+  HIPTRY(hipGetLastError());
+  if (nq == 0) return RK_OK;
+  if (bfilter_lds_bytes(ix) > kMaxLds) {
+    // too wide for the block-resident batched filter: one query at a time
+    for (int64_t i = 0; i < nq; ++i) {
+      rk_status st = enqueue_query(h, qs_dev + i * ix.d, ks[i], ids, cap, offs + i, offs + i + 1,
+                                   s, nullptr, nullptr);
+      if (st != RK_OK) return st;
+    }
+    return RK_OK;
+  }
+  const int64_t W = std::max<int64_t>((ix.n + 31) / 32, 1);
+  const int32_t chunk = (int32_t)std::max<int64_t>(
+      1, std::min<int64_t>({nq, (int64_t)kBatchChunkMax, kBitmapBudget / (W * 4)}));
+  rk_status st = ensure_batch_ws(h, chunk);
+  if (st != RK_OK) return st;
+  auto& b = h->bw;
+  for (int64_t c0 = 0; c0 < nq; c0 += chunk) {
+    const int32_t nc = (int32_t)std::min<int64_t>(chunk, nq - c0);
+    if ((st = stage_ks(h, ks + c0, nc, b.ks_dev, s)) != RK_OK) return st;
+    BatchView bv{};
+    bv.qs = qs_dev + c0 * ix.d;
+    bv.qn = b.qn; bv.perm = b.perm; bv.qt = b.qt; bv.qb = b.qb;
+    bv.qn_s = b.qn_s; bv.k_s = b.k_s; bv.nq_pad = (int32_t)round_up(nc, TILE);
+    bv.bits = b.bits; bv.W = W; bv.counts = b.counts; bv.all = b.all; bv.n = ix.n;
+    bv.npairs = b.npairs; bv.pair_cap = (int32_t)b.pair_cap;
+    bv.pair_u = b.pair_u; bv.pair_j = b.pair_j; bv.pair_s = b.pair_s;
+    bv.ctr = h->counting ? h->ctr_dev : nullptr;
+    { Timer t(h, s, K_BPREP); launch_bprep(ix, bv, b.ks_dev, nc, s); }
+    { Timer t(h, s, K_BFILTER); launch_bfilter(ix, bv, s); }
+    { Timer t(h, s, K_BPAIRS); launch_bpairs(ix, bv, s); }
+    { Timer t(h, s, K_BASSEMBLE); launch_bassemble(bv, nc, offs + c0, offs + c0, ids, cap, s); }
+    HIPTRY(hipGetLastError());
+    h->queries += nc;
   }
   return RK_OK;
 }
@@ -444,8 +613,6 @@ rk_status rk_index_rebuild(rk_index* h, int32_t k_max) {
   auto t0 = std::chrono::steady_clock::now();
   HIPTRY(hipStreamSynchronize(h->stream));
   for (void* p : {(void*)h->L64, (void*)h->L32, (void*)h->LB, (void*)h->bnorm}) h->dfree(p);
-  h->footprint -= (size_t)h->ix.kmax * h->ix.n_pad * (sizeof(double) + sizeof(float)) +
-                  (size_t)h->ix.kmax * h->ix.nB * sizeof(float) + (size_t)std::max(h->ix.nB, 1) * sizeof(float);
   h->ix.kmax = k_max;
   rk_status st = build_bounds(h);
   if (st != RK_OK) return st;
@@ -516,36 +683,17 @@ rk_status rk_reverse_kmips_trace(rk_index* h, const float* q, int32_t k, uint8_t
   return done(RK_OK);
 }
 
-static rk_status check_batch_ks(rk_index* h, const int32_t* ks, int64_t nq) {
-  int32_t need = 0;
-  for (int64_t i = 0; i < nq; ++i) {
-    if (ks[i] < 1) return fail(RK_E_INVAL, "k must be >= 1");
-    if (ks[i] > h->ix.kmax && ks[i] <= h->ix.m) need = std::max(need, ks[i]);
-  }
-  if (need) {
-    if (!h->opts.auto_rebuild) return fail(RK_E_KMAX, "k > k_max (build with a larger k_max or set auto_rebuild)");
-    return rk_index_rebuild(h, need);
-  }
-  return RK_OK;
-}
-
 rk_status rk_reverse_kmips_batch_dev(rk_index* h, const float* qs_dev, int64_t nq,
                                      const int32_t* ks, int64_t* offsets_dev, int32_t* ids_dev,
                                      int64_t cap, void* stream) {
   if (!h || nq < 0 || (nq > 0 && (!qs_dev || !ks)) || !offsets_dev || cap < 0 || (cap > 0 && !ids_dev))
     return fail(RK_E_INVAL, "NULL argument or negative size");
+  if (nq > INT32_MAX) return fail(RK_E_INVAL, "nq too large");
   rk_status st = check_batch_ks(h, ks, nq);
   if (st != RK_OK) return st;
   HIPTRY(hipSetDevice(h->device));
   hipStream_t s = stream ? (hipStream_t)stream : h->stream;
-  launch_set_i64(offsets_dev, 0, s);
-  HIPTRY(hipGetLastError());
-  for (int64_t i = 0; i < nq; ++i) {
-    st = enqueue_query(h, qs_dev + i * h->ix.d, ks[i], ids_dev, cap, offsets_dev + i,
-                       offsets_dev + i + 1, s, nullptr, nullptr);
-    if (st != RK_OK) return st;
-  }
-  return RK_OK;
+  return batch_enqueue(h, qs_dev, nq, ks, offsets_dev, ids_dev, cap, s);
 }
 
 rk_status rk_reverse_kmips_batch(rk_index* h, const float* qs, int64_t nq, const int32_t* ks,
@@ -580,6 +728,37 @@ rk_status rk_reverse_kmips_batch(rk_index* h, const float* qs, int64_t nq, const
   st = done(RK_OK);
   if (total > cap) return fail(RK_E_TRUNC, "results larger than cap");
   return st;
+}
+
+rk_status rk_index_set_timing(rk_index* h, int32_t max_launches) {
+  if (!h || max_launches < 0) return fail(RK_E_INVAL, "index is NULL or max_launches < 0");
+  HIPTRY(hipSetDevice(h->device));
+  HIPTRY(hipStreamSynchronize(h->stream));
+  h->ev_used.clear();
+  h->ev_next = 0;
+  const size_t want = (size_t)max_launches * 2;
+  while (h->ev_pool.size() < want) {
+    hipEvent_t e;
+    HIPTRY(hipEventCreate(&e));
+    h->ev_pool.push_back(e);
+  }
+  h->timing = max_launches > 0;
+  return RK_OK;
+}
+
+rk_status rk_index_kernel_times(rk_index* h, double* ms, int64_t* launches, int32_t nclass) {
+  if (!h || !ms || !launches || nclass < 1) return fail(RK_E_INVAL, "NULL argument");
+  for (int i = 0; i < nclass; ++i) { ms[i] = 0; launches[i] = 0; }
+  HIPTRY(hipSetDevice(h->device));
+  for (auto& u : h->ev_used) {
+    HIPTRY(hipEventSynchronize(u.second.second));
+    float t = 0;
+    HIPTRY(hipEventElapsedTime(&t, u.second.first, u.second.second));
+    if (u.first < nclass) { ms[u.first] += t; launches[u.first] += 1; }
+  }
+  h->ev_used.clear();
+  h->ev_next = 0;
+  return RK_OK;
 }
 
 rk_status rk_index_set_counting(rk_index* h, int32_t on) {

@@ -25,7 +25,8 @@ RK_FP32, RK_BF16 = 0, 1
 EXPORTS = [
     "rk_build_opts_default", "rk_build_index", "rk_build_index_dev", "rk_reverse_kmips",
     "rk_reverse_kmips_dev", "rk_reverse_kmips_batch", "rk_reverse_kmips_batch_dev",
-    "rk_reverse_kmips_trace", "rk_index_set_counting", "rk_index_stats",
+    "rk_reverse_kmips_trace", "rk_index_set_timing", "rk_index_kernel_times",
+    "rk_index_set_counting", "rk_index_stats",
     "rk_index_reset_counters", "rk_index_export", "rk_index_rebuild", "rk_index_footprint",
     "rk_index_free", "rk_last_error",
 ]
@@ -41,7 +42,8 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("lb_items", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("margin_rel", ctypes.c_double), ("cand_cap", ctypes.c_int32),
-                ("auto_rebuild", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("auto_rebuild", ctypes.c_int32), ("pair_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -67,12 +69,21 @@ _lib = None
 
 
 def lib():
-    """Load librkmips.so (raises if it has not been built)."""
+    """Load librkmips.so (raises if it has not been built).
+
+    PyTorch is imported first: its HIP runtime (libamdhip64.so.7) is then the
+    one the library binds to, so device pointers, streams and device-wide
+    synchronisation are shared with torch in one runtime.  Loading the
+    library before torch would bring in a second HIP/HSA runtime."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     pidx = ctypes.POINTER(ctypes.c_void_p)
@@ -92,6 +103,10 @@ def lib():
     L.rk_reverse_kmips_batch_dev.restype = ctypes.c_int
     L.rk_reverse_kmips_trace.argtypes = [vp, vp, i32, vp, vp]
     L.rk_reverse_kmips_trace.restype = ctypes.c_int
+    L.rk_index_set_timing.argtypes = [vp, i32]
+    L.rk_index_set_timing.restype = ctypes.c_int
+    L.rk_index_kernel_times.argtypes = [vp, vp, vp, i32]
+    L.rk_index_kernel_times.restype = ctypes.c_int
     L.rk_index_set_counting.argtypes = [vp, i32]
     L.rk_index_set_counting.restype = ctypes.c_int
     L.rk_index_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -118,7 +133,7 @@ def _check(status: int):
 
 
 def build_opts(precision="fp32", lb_items=0, device=0, margin_rel=0.0, cand_cap=0,
-               auto_rebuild=False) -> BuildOpts:
+               auto_rebuild=False, pair_cap=0) -> BuildOpts:
     o = BuildOpts()
     lib().rk_build_opts_default(ctypes.byref(o))
     o.precision = {"fp32": RK_FP32, "bf16": RK_BF16}[precision] if isinstance(precision, str) else int(precision)
@@ -127,6 +142,7 @@ def build_opts(precision="fp32", lb_items=0, device=0, margin_rel=0.0, cand_cap=
     o.margin_rel = float(margin_rel)
     o.cand_cap = int(cand_cap)
     o.auto_rebuild = 1 if auto_rebuild else 0
+    o.pair_cap = int(pair_cap)
     return o
 
 
@@ -232,6 +248,20 @@ class Index:
             ids_dev.numel(), ctypes.c_void_p(stream) if stream else None))
 
     # -- introspection --------------------------------------------------------
+    KERNEL_CLASSES = ("filter", "verify", "recheck", "finalize", "fill_all",
+                      "batch_prep", "batch_filter", "batch_pairs", "batch_assemble")
+
+    def set_timing(self, max_launches: int):
+        _check(lib().rk_index_set_timing(self._h, int(max_launches)))
+
+    def kernel_times(self) -> dict:
+        """{class: (total_ms, launches)} of the launches timed since set_timing."""
+        nc = len(self.KERNEL_CLASSES)
+        ms = np.zeros(nc, np.float64)
+        cnt = np.zeros(nc, np.int64)
+        _check(lib().rk_index_kernel_times(self._h, _ptr(ms), _ptr(cnt), nc))
+        return {c: (float(ms[i]), int(cnt[i])) for i, c in enumerate(self.KERNEL_CLASSES) if cnt[i]}
+
     def set_counting(self, on: bool = True):
         _check(lib().rk_index_set_counting(self._h, 1 if on else 0))
 
