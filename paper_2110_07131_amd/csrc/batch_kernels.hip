@@ -15,6 +15,7 @@
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace rk {
 
@@ -38,37 +39,98 @@ __global__ void k_bnorms(const float* __restrict__ qs, int32_t nq, int32_t d,
   if (lane == 0) qn[j] = f32_up(sqrt(s) * (1.0 + (double)(d + 4) * 0x1p-53));
 }
 
-// Single workgroup bitonic sort of the chunk's queries by descending norm
-// (ties by index); writes the sorted order perm[0..nq).
-__global__ void __launch_bounds__(1024) k_bsort(const float* __restrict__ qn, int32_t nq,
+// Sort of the chunk's queries by (k ascending, |q| descending, index), so
+// that a 64-query tile usually has one k and queries of similar norm: the
+// Lemma 3 test then prunes whole tiles and the epilogue reads one lower
+// bound per user.  One workgroup, bitonic network over N = 2^p <= 4096 keys;
+// thread t holds positions t + 1024 e.  Exchanges at stride >= 1024 are in
+// registers, 64..512 through LDS, < 64 by lane shuffles.
+__device__ __forceinline__ bool key_less(unsigned long long ka, int32_t ia, unsigned long long kb,
+                                         int32_t ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+__global__ void __launch_bounds__(1024) k_bsort(const float* __restrict__ qn,
+                                                const int32_t* __restrict__ ks, int32_t nq,
                                                 int32_t* __restrict__ perm) {
-  __shared__ float key[kBatchChunkMax];
-  __shared__ int32_t idx[kBatchChunkMax];
-  int P2 = 1;
-  while (P2 < nq) P2 <<= 1;
-  for (int i = threadIdx.x; i < P2; i += blockDim.x) {
-    key[i] = i < nq ? qn[i] : -INFINITY;
-    idx[i] = i < nq ? i : INT32_MAX;
+  __shared__ unsigned long long sk[kBatchChunkMax];
+  __shared__ int32_t si[kBatchChunkMax];
+  const int t = threadIdx.x;
+  int N = 64;
+  while (N < nq) N <<= 1;
+  const int E = N > 1024 ? N / 1024 : 1;  // elements per thread (1, 2 or 4)
+  const bool active = t < N;              // N < 1024: only the first N threads
+  unsigned long long key[4];
+  int32_t id[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int p = t + 1024 * e;
+    if (e < E && p < nq) {
+      // k ascending, then norm descending (norms are >= 0: larger float bits = larger)
+      key[e] = ((unsigned long long)(uint32_t)ks[p] << 32) | (uint32_t)(~__float_as_uint(qn[p]));
+      id[e] = p;
+    } else {
+      key[e] = ~0ull;
+      id[e] = INT32_MAX;
+    }
   }
-  __syncthreads();
-  for (int size = 2; size <= P2; size <<= 1) {
+  for (int size = 2; size <= N; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < P2; i += blockDim.x) {
-        const int pj = i ^ stride;
-        if (pj > i) {
-          const bool desc = (i & size) == 0;
-          // "a before b" in the final order: larger key, then smaller index
-          const bool i_first = key[i] > key[pj] || (key[i] == key[pj] && idx[i] < idx[pj]);
-          if (desc != i_first) {
-            float tk = key[i]; key[i] = key[pj]; key[pj] = tk;
-            int32_t ti = idx[i]; idx[i] = idx[pj]; idx[pj] = ti;
+      if (stride >= 1024) {
+        const int es = stride / 1024;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int f = e ^ es;
+          if (e < E && f > e && f < 4) {
+            const int p = t + 1024 * e;
+            const bool asc = (p & size) == 0;
+            const bool swap = asc ? key_less(key[f], id[f], key[e], id[e])
+                                  : key_less(key[e], id[e], key[f], id[f]);
+            if (swap) {
+              unsigned long long tk = key[e]; key[e] = key[f]; key[f] = tk;
+              int32_t ti = id[e]; id[e] = id[f]; id[f] = ti;
+            }
+          }
+        }
+      } else if (stride >= 64) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (e < E && active) { sk[t + 1024 * e] = key[e]; si[t + 1024 * e] = id[e]; }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (e < E && active) {
+            const int p = t + 1024 * e, q = p ^ stride;
+            const unsigned long long ko = sk[q];
+            const int32_t io = si[q];
+            const bool asc = (p & size) == 0;
+            const bool take_min = asc == (p < q);
+            const bool other_less = key_less(ko, io, key[e], id[e]);
+            if (take_min == other_less) { key[e] = ko; id[e] = io; }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (e < E) {
+            const int p = t + 1024 * e, q = p ^ stride;
+            const unsigned long long ko = __shfl_xor(key[e], stride);
+            const int32_t io = __shfl_xor(id[e], stride);
+            const bool asc = (p & size) == 0;
+            const bool take_min = asc == (p < q);
+            const bool other_less = key_less(ko, io, key[e], id[e]);
+            if (active && take_min == other_less) { key[e] = ko; id[e] = io; }
           }
         }
       }
-      __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < nq; i += blockDim.x) perm[i] = idx[i];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int p = t + 1024 * e;
+    if (e < E && active && p < nq) perm[p] = id[e];
+  }
 }
 
 // Query tiles in sorted order: fp32 [T][d][64] and (bf16 mode) [T][G][64][8],
@@ -85,7 +147,9 @@ __global__ void k_btile(const float* __restrict__ qs, const int32_t* __restrict_
   if (r >= nq_pad) return;
   const bool valid = r < nq;
   const int64_t src = valid ? perm[r] : 0;
-  for (int c = threadIdx.x; c < d; c += blockDim.x) qt[tix(r, c, d)] = valid ? qs[src * d + c] : 0.0f;
+  const int d2 = d + (d & 1);  // fp32 query tiles have an even number of rows
+  for (int c = threadIdx.x; c < d2; c += blockDim.x)
+    qt[tix(r, c, d2)] = (valid && c < d) ? qs[src * d + c] : 0.0f;
   if (qb) {
     const int64_t tile = r / TILE, lane = r % TILE;
     for (int c = threadIdx.x; c < d16; c += blockDim.x) {
@@ -105,211 +169,333 @@ __global__ void k_btile(const float* __restrict__ qs, const int32_t* __restrict_
 // Exact float64 decision of one (user, query) pair, used by a lane whose
 // undecided pair does not fit the pair list: with an exact table f(q,u)
 // against theta_k; otherwise the float64 linear scan (Algorithm 2).
-__device__ bool decide_f64(const DevIndex& ix, const BatchView& bv, int64_t r, int32_t jj) {
+__device__ __forceinline__ bool decide_f64(const DevIndex& ix, const BatchView& bv, int64_t r,
+                                           int32_t jj) {
   const int32_t jo = bv.perm[jj];
   const int k = bv.k_s[jj];
-  const float* q = bv.qs + (int64_t)jo * ix.d;
-  const float* u = ix.Qt + (r / TILE) * (int64_t)ix.d * TILE + (r % TILE);
-  double fq = 0.0;
-  for (int c = 0; c < ix.d; ++c) fq = fma((double)q[c], (double)u[(int64_t)c * TILE], fq);
+  const float* u = ix.Qrow + r * ix.d;
+  const double fq = dot64_rows(bv.qs + (int64_t)jo * ix.d, u, ix.d);
   if (ix.exact) return fq >= ix.L64[(int64_t)(k - 1) * ix.n_pad + r];
   const double csu = (double)ix.cs_inflate * (double)ix.normQ[r] * (1.0 + 0x1p-50);
   int beats = 0;
   for (int64_t j = 0; j < ix.m && beats < k; ++j) {
     if (csu * (double)ix.normP[j] <= fq) break;
-    const float* p = ix.Prow + j * ix.d;
-    double fp = 0.0;
-    for (int c = 0; c < ix.d; ++c) fp = fma((double)p[c], (double)u[(int64_t)c * TILE], fp);
-    beats += fp > fq;
+    beats += dot64_rows(ix.Prow + j * ix.d, u, ix.d) > fq;
   }
   return beats < k;
 }
 
 // ---------------------------------------------------------------------------
-// The batched filter.  Workgroup = 4 waves = one user block B; wave w takes
-// query tiles w, w+4, ...  Per tile: Lemma 3 for each of its 64 queries
-// (lane = query) gives a 64-bit mask of the queries that keep the block;
-// an all-zero mask skips the tile.  Otherwise the 64x64 score tile S[query][user]
-// is formed by four 32x32 MFMA blocks (A = queries, B = users), so a lane
-// holds two users (its column in both user halves) and 16 queries per half.
-template <bool BF16>
-__global__ void __launch_bounds__(256) k_bfilter(DevIndex ix, BatchView bv) {
-  extern __shared__ float lds[];
+// The batched filter.  Workgroup = 4 waves = one user block B (64 users).
+// It first evaluates Lemma 3 for every query of the chunk against the block
+// (one bit per query, a 64-bit mask per 64-query tile, kept in LDS) and then
+// walks only the tiles that have a live query.  All four waves work on the
+// same query tile, staged in LDS: wave w computes the 32x32 quarter (user
+// half w&1, query half w>>1) with MFMA, so a lane holds one user and 16
+// queries.  While a tile is processed the next live tile is being fetched
+// into registers; it is written to LDS between two barriers.  The epilogue
+// is the certified Lemma 1 test only; every pair it cannot reject is
+// appended to the pair list, decided afterwards by the recheck or the scan.
+constexpr int PF_VEC = 16;  // prefetch registers per thread: 16 x 16 bytes (64 KiB tiles)
+
+__device__ __forceinline__ int next_live(const unsigned long long* masks, int from, int nT) {
+  int T = from;
+  while (T < nT && masks[T] == 0ull) ++T;
+  return T;
+}
+
+// Prefetch of query tile T (tile_vecs 16-byte vectors, thread t takes
+// t, t+256, ...) and its metadata into registers, and their store to LDS.
+template <int NV>
+__device__ __forceinline__ void stage_tile(const u32x4* __restrict__ qsrc, const BatchView& bv,
+                                           int T, int tile_vecs, int t, u32x4 (&pf)[NV],
+                                           float& pf_n, int32_t& pf_k) {
+  const u32x4* src = qsrc + (int64_t)T * tile_vecs;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int i = v * 256 + t;
+    if (i < tile_vecs) pf[v] = src[i];
+  }
+  if (t < TILE) pf_n = bv.qn_s[(int64_t)T * TILE + t];
+  else if (t < 2 * TILE) pf_k = bv.k_s[(int64_t)T * TILE + t - TILE];
+}
+
+template <int NV>
+__device__ __forceinline__ void commit_tile(unsigned char* qbuf, float* meta_n, int32_t* meta_k,
+                                            int tile_vecs, int t, const u32x4 (&pf)[NV],
+                                            float pf_n, int32_t pf_k) {
+  u32x4* dst = (u32x4*)qbuf;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int i = v * 256 + t;
+    if (i < tile_vecs) dst[i] = pf[v];
+  }
+  if (t < TILE) meta_n[t] = pf_n;
+  else if (t < 2 * TILE) meta_k[t - TILE] = pf_k;
+}
+
+__device__ __forceinline__ int quarter_row(int qhalf, int half, int r) {
+  return qhalf * 32 + (r / 4) * 8 + half * 4 + (r % 4);
+}
+
+template <bool BF16, int NV>
+__global__ void __launch_bounds__(256, 2) k_bfilter(DevIndex ix, BatchView bv) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
   const int d = ix.d;
   const int64_t B = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int half = lane >> 5, col = lane & 31;
-  // LDS: user tile (fp32 [d][64] or bf16 [G][64][8]), L32 rows [kmax][64],
-  // LB column [kmax], |p_k| [kmax]
+  const int uh = wave & 1, qhalf = wave >> 1;
   const int G = ix.d16 / 8;
-  const size_t ubytes = BF16 ? (size_t)G * TILE * 8 * 2 : (size_t)d * TILE * 4;
-  float* uA = lds;
-  uint16_t* uB = (uint16_t*)lds;
-  float* Ll = (float*)((char*)lds + ubytes);
-  float* LBl = Ll + ix.kmax * TILE;
-  float* npk = LBl + ix.kmax;
+  const int d2 = d + (d & 1);  // fp32 tiles carry an even number of rows
+  const int tile_bytes = BF16 ? G * TILE * 16 : d2 * TILE * 4;
+  const int tile_vecs = tile_bytes / 16;
+  const int nT = bv.nq_pad / TILE;
+  unsigned char* p = lds_raw;
+  unsigned char* ubuf = p;
+  p += (tile_bytes + 15) / 16 * 16;
+  unsigned char* qbuf = p;
+  p += (tile_bytes + 15) / 16 * 16;
+  float* meta_n = (float*)p;
+  p += TILE * 4;
+  int32_t* meta_k = (int32_t*)p;
+  p += TILE * 4;
+  unsigned long long* masks = (unsigned long long*)p;
+  p += (kBatchChunkMax / TILE) * 8;
+  float* Ll = (float*)p;
+  p += ix.kmax * TILE * 4;
+  float* LBl = (float*)p;
+  p += ix.kmax * 4;
+  p += ix.kmax * 4;
+  float* Yl = (float*)p;  // [kmax][64] "yes" thresholds per (k, user)
+
+  // user tile, lower-bound rows and block minima of this block
   if (BF16) {
-    const uint4* src = (const uint4*)(ix.Qb + B * (int64_t)G * TILE * 8);
-    uint4* dst = (uint4*)uB;
-    for (int i = threadIdx.x; i < G * TILE; i += blockDim.x) dst[i] = src[i];
+    const u32x4* src = (const u32x4*)(ix.Qb + B * (int64_t)G * TILE * 8);
+    u32x4* dst = (u32x4*)ubuf;
+    for (int i = t; i < tile_vecs; i += 256) dst[i] = src[i];
   } else {
-    const float* src = ix.Qt + B * (int64_t)d * TILE;
-    for (int i = threadIdx.x; i < d * TILE; i += blockDim.x) uA[i] = src[i];
+    const u32x4* src = (const u32x4*)(ix.Qt + B * (int64_t)d * TILE);
+    u32x4* dst = (u32x4*)ubuf;
+    for (int i = t; i < d * TILE / 4; i += 256) dst[i] = src[i];
+    if (d & 1) ((float*)ubuf)[d * TILE + (t & 63)] = 0.f;  // zero pad row
   }
-  for (int i = threadIdx.x; i < ix.kmax * TILE; i += blockDim.x)
+  for (int i = t; i < ix.kmax * TILE; i += 256)
     Ll[i] = ix.L32[(int64_t)(i / TILE) * ix.n_pad + B * TILE + (i % TILE)];
-  for (int i = threadIdx.x; i < ix.kmax; i += blockDim.x) {
-    LBl[i] = ix.LB[(int64_t)i * ix.nB + B];
-    npk[i] = i < ix.m ? ix.normP[i] : 0.0f;
+  for (int i = t; i < ix.kmax; i += 256) LBl[i] = ix.LB[(int64_t)i * ix.nB + B];
+  // yes threshold of (k, user): exact table -> the float above L (>= theta_k);
+  // bounded table -> Lemma 2's bound cs_inflate |u|^ |p_k|^
+  for (int i = t; i < ix.kmax * TILE; i += 256) {
+    const int kk = i / TILE;
+    const float L = ix.L32[(int64_t)kk * ix.n_pad + B * TILE + (i % TILE)];
+    Yl[i] = ix.exact ? f32_next_up(L)
+                     : (ix.cs_inflate * ix.normQ[B * TILE + (i % TILE)]) *
+                           (kk < ix.m ? ix.normP[kk] : INFINITY);
   }
   __syncthreads();
 
-  const float bn = ix.bnorm[B];
-  const float csb = ix.cs_inflate * bn;
-  // the lane's two users
-  const int64_t u0 = B * TILE + col, u1 = u0 + 32;
-  const bool v0 = u0 < ix.n, v1 = u1 < ix.n;
-  const float nu0 = ix.normQ[u0], nu1 = ix.normQ[u1];
-  const float a0 = ix.eps_rel * nu0, a1 = ix.eps_rel * nu1;
-  const float c0 = ix.cs_inflate * nu0, c1 = ix.cs_inflate * nu1;
-  const int32_t o0 = v0 ? ix.permQ[u0] : 0, o1 = v1 ? ix.permQ[u1] : 0;
-  const int nT = bv.nq_pad / TILE;
-  unsigned long long c_vis = 0, c_pr = 0, c_users = 0, c_no1 = 0, c_yes2 = 0, c_yesT = 0, c_und = 0;
-
-  for (int T = wave; T < nT; T += 4) {
-    // Lemma 3 for query T*64 + lane
-    const int64_t jq = (int64_t)T * TILE + lane;
-    const int kq = bv.k_s[jq];
-    const float nqq = bv.qn_s[jq];
+  // Lemma 3 for every query of the chunk: query j lives iff
+  // cs_inflate * |u_first| * |q_j| >= L^k(B).
+  const float csb = ix.cs_inflate * ix.bnorm[B];
+  unsigned long long c_vis = 0, c_pr = 0;
+  for (int base = 0; base < bv.nq_pad; base += 256) {
+    const int j = base + t;
+    int kq = 0;
+    float nqq = 0.f;
+    if (j < bv.nq_pad) {
+      kq = bv.k_s[j];
+      nqq = bv.qn_s[j];
+    }
     const bool live = kq > 0 && !(csb * nqq < LBl[kq > 0 ? kq - 1 : 0]);
-    const unsigned long long mask = __ballot(live);
-    c_vis += __popcll(__ballot(kq > 0));
-    c_pr += __popcll(__ballot(kq > 0 && !live));
-    if (!mask) continue;
+    const unsigned long long m = __ballot(live);
+    if (lane == 0 && base + wave * TILE < bv.nq_pad) masks[(base + wave * TILE) / TILE] = m;
+    c_vis += kq > 0;
+    c_pr += kq > 0 && !live;
+  }
+  __syncthreads();
 
-    f32x16 acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};  // [query half][user half]
+  const int64_t u = B * TILE + uh * 32 + col;  // this lane's user
+  const bool valid = u < ix.n;
+  const float a_u = ix.eps_rel * ix.normQ[u];
+  const int32_t orig_u = valid ? ix.permQ[u] : 0;
+  unsigned long long c_users = 0, c_rest = 0, c_yes = 0;
+
+  // prefetch registers for the next tile (tile bytes + 512 bytes of metadata)
+  u32x4 pf[NV];
+  float pf_n = 0.f;
+  int32_t pf_k = 0;
+  const u32x4* qsrc = BF16 ? (const u32x4*)bv.qb : (const u32x4*)bv.qt;
+
+  int T = next_live(masks, 0, nT);
+  if (T < nT) {
+    stage_tile(qsrc, bv, T, tile_vecs, t, pf, pf_n, pf_k);
+    commit_tile(qbuf, meta_n, meta_k, tile_vecs, t, pf, pf_n, pf_k);
+  }
+  __syncthreads();
+  int Tn = next_live(masks, T + 1, nT);
+  if (Tn < nT) stage_tile(qsrc, bv, Tn, tile_vecs, t, pf, pf_n, pf_k);
+
+  while (T < nT) {
+    const unsigned long long mask = masks[T];
+    // this wave's query half may have no live query at all
+    const uint32_t hmask = (uint32_t)(mask >> (qhalf * 32));
+    if (hmask != 0u) {
+    // ---- scores of the quarter: S[query][user], 32 x 32 (two accumulators
+    // alternate over the k-steps and are summed at the end)
+    f32x16 acc = {}, acc2 = {};
     if (!BF16) {
-      const float* qt = bv.qt + (int64_t)T * d * TILE;
-      for (int ks = 0; ks < (d + 1) / 2; ++ks) {
-        const int c = 2 * ks + half;
-        float qa0 = 0.f, qa1 = 0.f, ub0 = 0.f, ub1 = 0.f;
-        if (c < d) {
-          qa0 = qt[c * TILE + col];
-          qa1 = qt[c * TILE + 32 + col];
-          ub0 = uA[c * TILE + col];
-          ub1 = uA[c * TILE + 32 + col];
+      const float* qf = (const float*)qbuf + qhalf * 32 + col + half * TILE;
+      const float* uf = (const float*)ubuf + uh * 32 + col + half * TILE;
+      const int nsteps = d2 / 2;
+      int ks = 0;
+      for (; ks + 4 <= nsteps; ks += 4) {
+        float a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          a[i] = qf[(2 * (ks + i)) * TILE];
+          b[i] = uf[(2 * (ks + i)) * TILE];
         }
-        acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(qa0, ub0, acc00, 0, 0, 0);
-        acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(qa0, ub1, acc01, 0, 0, 0);
-        acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(qa1, ub0, acc10, 0, 0, 0);
-        acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(qa1, ub1, acc11, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[0], acc, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b[1], acc2, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], b[2], acc, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], b[3], acc2, 0, 0, 0);
       }
+      for (; ks < nsteps; ++ks)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(qf[2 * ks * TILE], uf[2 * ks * TILE], acc, 0, 0, 0);
     } else {
-      const uint4* qb = (const uint4*)(bv.qb + (int64_t)T * G * TILE * 8);
-      const uint4* ub = (const uint4*)uB;
-      for (int ks = 0; ks < G / 2; ++ks) {
-        const int g = 2 * ks + half;
-        const uint4 x0 = qb[g * TILE + col], x1 = qb[g * TILE + 32 + col];
-        const uint4 y0 = ub[g * TILE + col], y1 = ub[g * TILE + 32 + col];
-        bf16x8 qa0, qa1, ub0, ub1;
-        __builtin_memcpy(&qa0, &x0, 16);
-        __builtin_memcpy(&qa1, &x1, 16);
-        __builtin_memcpy(&ub0, &y0, 16);
-        __builtin_memcpy(&ub1, &y1, 16);
-        acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa0, ub0, acc00, 0, 0, 0);
-        acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa0, ub1, acc01, 0, 0, 0);
-        acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa1, ub0, acc10, 0, 0, 0);
-        acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa1, ub1, acc11, 0, 0, 0);
+      const bf16x8* qv = (const bf16x8*)qbuf + qhalf * 32 + col + half * TILE;
+      const bf16x8* uv = (const bf16x8*)ubuf + uh * 32 + col + half * TILE;
+      const int nsteps = G / 2;
+      int ks = 0;
+      for (; ks + 2 <= nsteps; ks += 2) {
+        const bf16x8 a0 = qv[2 * ks * TILE], b0 = uv[2 * ks * TILE];
+        const bf16x8 a1 = qv[(2 * ks + 2) * TILE], b1 = uv[(2 * ks + 2) * TILE];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc2, 0, 0, 0);
+      }
+      if (ks < nsteps)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qv[2 * ks * TILE], uv[2 * ks * TILE], acc, 0, 0, 0);
+    }
+    acc += acc2;
+
+    // ---- certified tests.  Lemma 1: "no" iff s + e < L.  "Yes" iff
+    // s - e >= Y, with Y the float above L (exact table: f >= theta_k) or
+    // the Cauchy-Schwarz bound of the k-th item (Lemma 2), both per (k,
+    // user) in LDS.  e = eps|u||q| + eps_abs; both tests round relative to
+    // |u||q|, which the slack inside eps covers.
+    // the lane's rows are qhalf*32 + g*8 + half*4 + i  (r = 4g + i)
+    const uint32_t hm = hmask >> (half * 4);
+    const uint32_t cells = (hm & 0xFu) | ((hm >> 4) & 0xF0u) | ((hm >> 8) & 0xF00u) |
+                           ((hm >> 12) & 0xF000u);
+    const int ucol = uh * 32 + col;
+    uint32_t rest = 0;
+    float ev[16];
+    int kv[16];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int rb = quarter_row(qhalf, half, g * 4);
+      const float4 n4 = *(const float4*)(meta_n + rb);
+      const int4 k4 = *(const int4*)(meta_k + rb);
+      const float nqs[4] = {n4.x, n4.y, n4.z, n4.w};
+      const int kks[4] = {k4.x, k4.y, k4.z, k4.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = g * 4 + i;
+        kv[r] = max(kks[i], 1);
+        ev[r] = fmaf(a_u, nqs[i], ix.eps_abs);
+        const float L = Ll[(kv[r] - 1) * TILE + ucol];
+        rest |= (uint32_t)!(acc[r] + ev[r] < L) << r;
       }
     }
-
-    // Epilogue: lane holds queries (r/4)*8 + half*4 + r%4 (+32 for the second
-    // query half) against users col and 32 + col.
-#pragma unroll
-    for (int qh = 0; qh < 2; ++qh) {
+    rest &= valid ? cells : 0u;
+    uint32_t yes = 0;
+    if (__ballot(rest != 0u)) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = qh * 32 + (r / 4) * 8 + half * 4 + (r % 4);
-        const bool cell = (mask >> row) & 1ull;
-        const int64_t jj = (int64_t)T * TILE + row;  // sorted query position
-        const int kk = cell ? bv.k_s[jj] : 1;
-        const float nqj = cell ? bv.qn_s[jj] : 0.f;
-        const float Lk0 = Ll[(kk - 1) * TILE + col], Lk1 = Ll[(kk - 1) * TILE + 32 + col];
-        const float s0 = qh ? acc10[r] : acc00[r];
-        const float s1 = qh ? acc11[r] : acc01[r];
-        const float e0 = fmaf(a0, nqj, ix.eps_abs), e1 = fmaf(a1, nqj, ix.eps_abs);
-        const bool x0 = cell && v0, x1 = cell && v1;
-        const bool no0 = x0 && (s0 + e0 < Lk0), no1 = x1 && (s1 + e1 < Lk1);
-        const bool rest0 = x0 && !no0, rest1 = x1 && !no1;
-        if (bv.ctr) {
-          c_users += (unsigned)x0 + (unsigned)x1;
-          c_no1 += (unsigned)no0 + (unsigned)no1;
-        }
-        if (__ballot(rest0 || rest1) == 0ull) continue;
-        const float pk = npk[kk - 1];
-        const bool y20 = rest0 && (s0 - e0 >= c0 * pk);
-        const bool y21 = rest1 && (s1 - e1 >= c1 * pk);
-        const bool yT0 = rest0 && !y20 && ix.exact && (s0 - e0 >= f32_next_up(Lk0));
-        const bool yT1 = rest1 && !y21 && ix.exact && (s1 - e1 >= f32_next_up(Lk1));
-        const bool un0 = rest0 && !y20 && !yT0, un1 = rest1 && !y21 && !yT1;
-        const int32_t jo = (y20 || yT0 || y21 || yT1 || un0 || un1) ? bv.perm[jj] : 0;  // chunk-local query id
-        if (y20 || yT0) {
-          atomicOr(&bv.bits[(int64_t)jo * bv.W + (o0 >> 5)], 1u << (o0 & 31));
-          atomicAdd(&bv.counts[jo], 1ull);
-        }
-        if (y21 || yT1) {
-          atomicOr(&bv.bits[(int64_t)jo * bv.W + (o1 >> 5)], 1u << (o1 & 31));
-          atomicAdd(&bv.counts[jo], 1ull);
-        }
-        // undecided pairs: wave-aggregated appends
+        const float Y = Yl[(kv[r] - 1) * TILE + ucol];
+        yes |= (uint32_t)(acc[r] - ev[r] >= Y) << r;
+      }
+      yes &= rest;
+    }
+    const uint32_t und = rest & ~yes;
+    if (bv.ctr) {
+      c_users += valid ? __popc(cells) : 0;
+      c_rest += __popc(rest);
+      c_yes += __popc(yes);
+    }
+    // ---- certified members: result bits
+    uint32_t yy = yes;
+    while (yy) {
+      const int r = __ffs(yy) - 1;
+      yy &= yy - 1;
+      const int32_t jo = bv.perm[(int64_t)T * TILE + quarter_row(qhalf, half, r)];
+      atomicOr(&bv.bits[(int64_t)jo * bv.W + (orig_u >> 5)], 1u << (orig_u & 31));
+      atomicAdd(&bv.counts[jo], 1ull);
+    }
+    // ---- undecided pairs: appended (one atomic per wave)
+    if (__ballot(und != 0u)) {
+      const int cnt = __popc(und);
+      int incl = cnt;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
+      }
+      int base = 0;
+      if (lane == 63) base = atomicAdd(bv.npairs, incl);
+      base = __shfl(base, 63);
+      int pos = base + incl - cnt;
+      uint32_t ovf = 0;  // pairs beyond the list's capacity
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const bool un = h ? un1 : un0;
-          const unsigned long long um = __ballot(un);
-          if (!um) continue;
-          const int leader = __ffsll((long long)um) - 1;
-          int base = 0;
-          if (lane == leader) base = atomicAdd(bv.npairs, (int)__popcll(um));
-          base = __shfl(base, leader);
-          if (un) {
-            const int pos = base + __popcll(um & lanemask_lt_b());
-            const int64_t uu = h ? u1 : u0;
-            if (pos < bv.pair_cap) {
-              bv.pair_u[pos] = (int32_t)uu;
-              bv.pair_j[pos] = (int32_t)jj;
-              bv.pair_s[pos] = h ? s1 : s0;
-            } else if (decide_f64(ix, bv, uu, (int32_t)jj)) {
-              const int32_t oo = h ? o1 : o0;
-              atomicOr(&bv.bits[(int64_t)jo * bv.W + (oo >> 5)], 1u << (oo & 31));
-              atomicAdd(&bv.counts[jo], 1ull);
-            }
+      for (int r = 0; r < 16; ++r) {
+        if ((und >> r) & 1u) {
+          if (pos < bv.pair_cap) {
+            bv.pair_u[pos] = (int32_t)u;
+            bv.pair_j[pos] = (int32_t)((int64_t)T * TILE + quarter_row(qhalf, half, r));
+            bv.pair_s[pos] = acc[r];
+          } else {
+            ovf |= 1u << r;
           }
+          ++pos;
         }
-        if (bv.ctr) {
-          c_yes2 += (unsigned)y20 + (unsigned)y21;
-          c_yesT += (unsigned)yT0 + (unsigned)yT1;
-          c_und += (unsigned)un0 + (unsigned)un1;
+      }
+      while (ovf) {  // rare: decide in float64 here
+        const int r = __ffs(ovf) - 1;
+        ovf &= ovf - 1;
+        const int32_t jj = (int32_t)((int64_t)T * TILE + quarter_row(qhalf, half, r));
+        if (decide_f64(ix, bv, u, jj)) {
+          const int32_t jo = bv.perm[jj];
+          atomicOr(&bv.bits[(int64_t)jo * bv.W + (orig_u >> 5)], 1u << (orig_u & 31));
+          atomicAdd(&bv.counts[jo], 1ull);
         }
       }
     }
+
+    }  // hmask
+
+    // ---- next tile: prefetched registers -> LDS
+    __syncthreads();
+    if (Tn < nT) commit_tile(qbuf, meta_n, meta_k, tile_vecs, t, pf, pf_n, pf_k);
+    T = Tn;
+    Tn = next_live(masks, T + 1, nT);
+    __syncthreads();
+    if (Tn < nT) stage_tile(qsrc, bv, Tn, tile_vecs, t, pf, pf_n, pf_k);
   }
+
   if (bv.ctr) {
-    // per-lane partial counts -> one atomic per counter per wave
     for (int off = 32; off > 0; off >>= 1) {
       c_users += __shfl_xor(c_users, off);
-      c_no1 += __shfl_xor(c_no1, off);
-      c_yes2 += __shfl_xor(c_yes2, off);
-      c_yesT += __shfl_xor(c_yesT, off);
-      c_und += __shfl_xor(c_und, off);
+      c_rest += __shfl_xor(c_rest, off);
+      c_yes += __shfl_xor(c_yes, off);
+      c_vis += __shfl_xor(c_vis, off);
+      c_pr += __shfl_xor(c_pr, off);
     }
     if (lane == 0) {
       atomicAdd(&bv.ctr[C_BLOCKS], c_vis);
       atomicAdd(&bv.ctr[C_PRUNED], c_pr);
       atomicAdd(&bv.ctr[C_USERS], c_users);
-      atomicAdd(&bv.ctr[C_L1NO], c_no1);
-      atomicAdd(&bv.ctr[C_L2YES], c_yes2);
-      atomicAdd(&bv.ctr[C_TYES], c_yesT);
-      atomicAdd(&bv.ctr[ix.exact ? C_RCHK : C_SURV], c_und);
+      atomicAdd(&bv.ctr[C_L1NO], c_users - c_rest);
+      atomicAdd(&bv.ctr[ix.exact ? C_TYES : C_L2YES], c_yes);
+      atomicAdd(&bv.ctr[ix.exact ? C_RCHK : C_SURV], c_rest - c_yes);
     }
   }
 }
@@ -328,18 +514,20 @@ __device__ __forceinline__ void set_pair_result(const BatchView& bv, const DevIn
 
 __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView bv) {
   const int np = min(*bv.npairs, bv.pair_cap);
+  unsigned long long yes_count = 0;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < np;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = bv.pair_u[t];
-    const int32_t jj = bv.pair_j[t];
+    const int64_t jj = bv.pair_j[t];
     const int32_t jo = bv.perm[jj];
-    const float* q = bv.qs + (int64_t)jo * ix.d;
-    const float* u = ix.Qt + (r / TILE) * (int64_t)ix.d * TILE + (r % TILE);
-    double fq = 0.0;
-    for (int c = 0; c < ix.d; ++c) fq = fma((double)q[c], (double)u[(int64_t)c * TILE], fq);
+    const double fq = dot64_rows(bv.qs + (int64_t)jo * ix.d, ix.Qrow + r * ix.d, ix.d);
     const int k = bv.k_s[jj];
-    if (fq >= ix.L64[(int64_t)(k - 1) * ix.n_pad + r]) set_pair_result(bv, ix, r, jo);
+    if (fq >= ix.L64[(int64_t)(k - 1) * ix.n_pad + r]) {
+      set_pair_result(bv, ix, r, jo);
+      ++yes_count;
+    }
   }
+  if (bv.ctr && yes_count) atomicAdd(&bv.ctr[C_TYES], yes_count);
 }
 
 template <bool BF16>
@@ -356,6 +544,15 @@ __global__ void __launch_bounds__(256) k_bverify(DevIndex ix, BatchView bv) {
     const float nu = ix.normQ[r];
     const float euq = margin(ix, nu, nq);
     const float sl = s - euq;
+    const int32_t jo0 = bv.perm[jj];
+    // Lemma 2 (certified): items from the k-th on cannot beat q.
+    if (sl >= (ix.cs_inflate * nu) * ix.normP[k - 1]) {
+      if (lane == 0) {
+        set_pair_result(bv, ix, r, jo0);
+        if (bv.ctr) atomicAdd(&bv.ctr[C_L2YES], 1ull);
+      }
+      continue;
+    }
     int64_t lo = 0, hi = ix.m;
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;
@@ -364,6 +561,7 @@ __global__ void __launch_bounds__(256) k_bverify(DevIndex ix, BatchView bv) {
     }
     const int64_t stop = lo;
     int beats = 0, unsure = 0;
+    int64_t scanned = 0;
     const int64_t ub = r / TILE, ul = r % TILE;
     for (int64_t t0 = 0; t0 < stop && beats < k; t0 += TILE) {
       const int64_t j = t0 + lane;
@@ -403,28 +601,25 @@ __global__ void __launch_bounds__(256) k_bverify(DevIndex ix, BatchView bv) {
       const bool unc = inb && !beat && !(diff <= -tol);
       beats += __popcll(__ballot(beat));
       unsure += __popcll(__ballot(unc));
+      scanned += (stop - t0 < TILE) ? (stop - t0) : TILE;
     }
-    const int32_t jo = bv.perm[jj];
+    if (bv.ctr && lane == 0) atomicAdd(&bv.ctr[C_SCAN], (unsigned long long)scanned);
+    const int32_t jo = jo0;
     if (beats >= k) continue;
     if (beats + unsure < k) {
       if (lane == 0) set_pair_result(bv, ix, r, jo);
       continue;
     }
     // float64 scan in this wave: lane = item, counts up to k
-    const float* q = bv.qs + (int64_t)jo * ix.d;
-    const float* u = ix.Qt + ub * (int64_t)ix.d * TILE + ul;
-    double fq = 0.0;
-    for (int c = 0; c < ix.d; ++c) fq = fma((double)q[c], (double)u[(int64_t)c * TILE], fq);
+    const float* u = ix.Qrow + r * ix.d;
+    const double fq = dot64_rows(bv.qs + (int64_t)jo * ix.d, u, ix.d);
     const double csu = (double)ix.cs_inflate * (double)nu * (1.0 + 0x1p-50);
     int b64 = 0;
     for (int64_t t0 = 0; t0 < ix.m && b64 < k; t0 += TILE) {
       const int64_t j = t0 + lane;
       bool beat = false;
       if (j < ix.m && csu * (double)ix.normP[j] > fq) {
-        const float* p = ix.Prow + j * ix.d;
-        double fp = 0.0;
-        for (int c = 0; c < ix.d; ++c) fp = fma((double)p[c], (double)u[(int64_t)c * TILE], fp);
-        beat = fp > fq;
+        beat = dot64_rows(ix.Prow + j * ix.d, u, ix.d) > fq;
       }
       b64 += __popcll(__ballot(beat));
       // items are norm-sorted: once a whole tile is past the bound, stop
@@ -465,41 +660,49 @@ __global__ void __launch_bounds__(1024) k_bscan(const unsigned long long* __rest
 
 __global__ void __launch_bounds__(256) k_bassemble(BatchView bv, const int64_t* __restrict__ offs,
                                                    int32_t* __restrict__ ids, int64_t cap) {
-  __shared__ int64_t part[256];
+  // Each wave owns a contiguous quarter of the query's bitmap row; lanes read
+  // consecutive words (coalesced).  Pass 1 counts the quarter, pass 2 writes
+  // ids with a wave-wide inclusive scan of per-word counts.
+  __shared__ int64_t wbase[4];
   const int32_t j = blockIdx.x;
-  uint32_t* row = bv.bits + (int64_t)j * bv.W;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   if (bv.all[j]) {  // k > m: every user, ascending
     const int64_t b0 = offs[j];
     for (int64_t i = t; i < bv.n && b0 + i < cap; i += blockDim.x) ids[b0 + i] = (int32_t)i;
     if (t == 0 && bv.ctr) atomicAdd(&bv.ctr[C_RES], (unsigned long long)bv.n);
     return;
   }
-  const int64_t w0 = bv.W * t / 256, w1 = bv.W * (t + 1) / 256;
-  int64_t c = 0;
-  for (int64_t w = w0; w < w1; ++w) c += __popc(row[w]);
-  part[t] = c;
+  uint32_t* row = bv.bits + (int64_t)j * bv.W;
+  const int64_t w0 = bv.W * wave / 4, w1 = bv.W * (wave + 1) / 4;
+  int c = 0;
+  for (int64_t w = w0 + lane; w < w1; w += 64) c += __popc(row[w]);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if (lane == 0) wbase[wave] = c;
   __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    int64_t v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int64_t pos = offs[j] + part[t] - c;
-  for (int64_t w = w0; w < w1; ++w) {
-    uint32_t bits = row[w];
-    if (!bits) continue;
-    row[w] = 0u;
+  int64_t pos = offs[j];
+  for (int i = 0; i < wave; ++i) pos += wbase[i];
+  const int64_t total = wbase[0] + wbase[1] + wbase[2] + wbase[3];
+  for (int64_t wb = w0; wb < w1; wb += 64) {
+    const int64_t w = wb + lane;
+    uint32_t bits = w < w1 ? row[w] : 0u;
+    const int pc = __popc(bits);
+    int incl = pc;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off);
+      if (lane >= off) incl += v;
+    }
+    int64_t p = pos + incl - pc;
+    if (bits) row[w] = 0u;
     while (bits) {
       const int b = __ffs(bits) - 1;
       bits &= bits - 1;
-      if (pos < cap) ids[pos] = (int32_t)(w * 32 + b);
-      ++pos;
+      if (p < cap) ids[p] = (int32_t)(w * 32 + b);
+      ++p;
     }
+    pos += __shfl(incl, 63);
   }
   if (t == 0) {
-    if (bv.ctr) atomicAdd(&bv.ctr[C_RES], (unsigned long long)part[255]);
+    if (bv.ctr) atomicAdd(&bv.ctr[C_RES], (unsigned long long)total);
     bv.counts[j] = 0ull;
   }
 }
@@ -509,7 +712,7 @@ void launch_bprep(const DevIndex& ix, const BatchView& bv, const int32_t* ks_dev
                   hipStream_t s) {
   hipLaunchKernelGGL(k_bnorms, dim3((nq + 3) / 4), dim3(256), 0, s, bv.qs, nq, ix.d, bv.qn,
                      bv.npairs);
-  hipLaunchKernelGGL(k_bsort, dim3(1), dim3(1024), 0, s, bv.qn, nq, bv.perm);
+  hipLaunchKernelGGL(k_bsort, dim3(1), dim3(1024), 0, s, bv.qn, ks_dev, nq, bv.perm);
   dim3 blk(64, 4);
   hipLaunchKernelGGL(k_btile, dim3((bv.nq_pad + 3) / 4), blk, 0, s, bv.qs, ks_dev, bv.qn,
                      bv.perm, nq, bv.nq_pad, ix.d, ix.d16, ix.m, bv.qt, ix.bf16 ? bv.qb : nullptr,
@@ -517,21 +720,37 @@ void launch_bprep(const DevIndex& ix, const BatchView& bv, const int32_t* ks_dev
 }
 
 size_t bfilter_lds_bytes(const DevIndex& ix) {
-  const size_t ubytes = ix.bf16 ? (size_t)(ix.d16 / 8) * TILE * 16 : (size_t)ix.d * TILE * 4;
-  return ubytes + (size_t)ix.kmax * TILE * 4 + (size_t)ix.kmax * 8;
+  const size_t tile = ix.bf16 ? (size_t)(ix.d16 / 8) * TILE * 16 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
+  return 2 * ((tile + 15) / 16 * 16) + 2 * TILE * 4 + (kBatchChunkMax / TILE) * 8 +
+         2 * (size_t)ix.kmax * TILE * 4 + (size_t)ix.kmax * 8;
+}
+
+// Largest query tile the filter's prefetch registers hold.
+size_t bfilter_max_tile_bytes() { return (size_t)PF_VEC * 256 * 16; }
+
+template <bool BF16, int NV>
+static void bfilter_nv(const DevIndex& ix, const BatchView& bv, size_t lds, hipStream_t s) {
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_bfilter<BF16, NV>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_bfilter<BF16, NV>), dim3(ix.nB), dim3(256), lds, s, ix, bv);
+}
+
+template <bool BF16>
+static void bfilter_prec(const DevIndex& ix, const BatchView& bv, size_t lds, hipStream_t s) {
+  const size_t tile = BF16 ? (size_t)(ix.d16 / 8) * TILE * 16 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
+  const size_t per_thread = (tile / 16 + 255) / 256;  // 16-byte vectors per thread
+  if (per_thread <= 2) bfilter_nv<BF16, 2>(ix, bv, lds, s);
+  else if (per_thread <= 4) bfilter_nv<BF16, 4>(ix, bv, lds, s);
+  else if (per_thread <= 8) bfilter_nv<BF16, 8>(ix, bv, lds, s);
+  else bfilter_nv<BF16, 16>(ix, bv, lds, s);
 }
 
 void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
   if (ix.nB == 0) return;
   const size_t lds = bfilter_lds_bytes(ix);
-  if (lds > 65536) {
-    (void)hipFuncSetAttribute((const void*)k_bfilter<true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)k_bfilter<false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  }
-  if (ix.bf16) hipLaunchKernelGGL(k_bfilter<true>, dim3(ix.nB), dim3(256), lds, s, ix, bv);
-  else hipLaunchKernelGGL(k_bfilter<false>, dim3(ix.nB), dim3(256), lds, s, ix, bv);
+  if (ix.bf16) bfilter_prec<true>(ix, bv, lds, s);
+  else bfilter_prec<false>(ix, bv, lds, s);
 }
 
 void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s) {

@@ -288,9 +288,8 @@ __global__ void __launch_bounds__(256) k_recheck(DevIndex ix, const float* __res
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = ws.rchk_idx[t];
-    const float* u = ix.Qt + (r / TILE) * (int64_t)ix.d * TILE + (r % TILE);
-    double fq = 0.0;
-    for (int c = 0; c < ix.d; ++c) fq = fma((double)q[c], (double)u[(int64_t)c * TILE], fq);
+    const float* u = ix.Qrow + r * ix.d;
+    const double fq = dot64_rows(q, u, ix.d);
     bool yes;
     if (ix.exact) {
       yes = fq >= ix.L64[(int64_t)(k - 1) * ix.n_pad + r];
@@ -299,10 +298,7 @@ __global__ void __launch_bounds__(256) k_recheck(DevIndex ix, const float* __res
       int beats = 0;
       for (int64_t j = 0; j < ix.m && beats < k; ++j) {
         if (cs * nu * (double)ix.normP[j] * (1.0 + 0x1p-50) <= fq) break;
-        const float* p = ix.Prow + j * ix.d;
-        double fp = 0.0;
-        for (int c = 0; c < ix.d; ++c) fp = fma((double)p[c], (double)u[(int64_t)c * TILE], fp);
-        beats += fp > fq;
+        beats += dot64_rows(ix.Prow + j * ix.d, u, ix.d) > fq;
       }
       yes = beats < k;
     }

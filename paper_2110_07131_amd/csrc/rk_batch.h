@@ -31,6 +31,7 @@ struct BatchView {
 void launch_bprep(const DevIndex& ix, const BatchView& bv, const int32_t* ks_dev, int32_t nq,
                   hipStream_t s);
 size_t bfilter_lds_bytes(const DevIndex& ix);
+size_t bfilter_max_tile_bytes();
 void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 // offs[0] must hold the chunk's first offset; writes offs[1..nq] and ids.

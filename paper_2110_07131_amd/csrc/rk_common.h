@@ -63,6 +63,7 @@ struct DevIndex {
   int32_t exact;         // 1 if L holds the exact k_max largest values over P
   int32_t bf16;          // 1 if the bulk products use the bf16 copies
   const float* Qt;       // tiled fp32 users
+  const float* Qrow;     // [n][d] sorted users, row-major (float64 rechecks)
   const uint16_t* Qb;    // tiled bf16 users (bf16 mode)
   const float* normQ;    // [n_pad] norm rounded up (0 for padding)
   const int32_t* permQ;  // [n] original id of sorted user
@@ -79,6 +80,27 @@ struct DevIndex {
   float eps_abs;         // absolute slack (underflow)
   float cs_inflate;      // 1 + gamma64_d + slack: f(p,u) <= cs_inflate*|u|^*|p|^
 };
+
+// f(x, y) in float64, index order, from two contiguous float32 rows: the
+// inner product of the definition (each product is exact in double; the
+// loads are batched ahead of the sequential accumulation).
+__device__ __forceinline__ double dot64_rows(const float* __restrict__ x,
+                                             const float* __restrict__ y, int d) {
+  double s = 0.0;
+  int c0 = 0;
+  for (; c0 + 8 <= d; c0 += 8) {
+    float xv[8], yv[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      xv[i] = x[c0 + i];
+      yv[i] = y[c0 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s = fma((double)xv[i], (double)yv[i], s);
+  }
+  for (; c0 < d; ++c0) s = fma((double)x[c0], (double)y[c0], s);
+  return s;
+}
 
 // |approx - f| <= margin(|u|^, |x|^) for every bulk inner product.
 __device__ __forceinline__ float margin(const DevIndex& ix, float nu, float nx) {

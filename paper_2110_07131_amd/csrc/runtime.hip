@@ -64,7 +64,7 @@ struct rk_index {
   std::vector<void*> hbufs;
   size_t footprint = 0;
   // owned device arrays
-  float *Qt = nullptr, *normQ = nullptr, *Pt = nullptr, *Prow = nullptr, *normP = nullptr;
+  float *Qt = nullptr, *Qrow = nullptr, *normQ = nullptr, *Pt = nullptr, *Prow = nullptr, *normP = nullptr;
   uint16_t *Qb = nullptr, *Pb = nullptr;
   int32_t *permQ = nullptr, *permP = nullptr;
   double *s2Q = nullptr, *s2P = nullptr, *L64 = nullptr;
@@ -349,16 +349,17 @@ rk_status build_impl(const float* Q, int64_t n, const float* P, int64_t m, int32
   TTRY(h->dalloc(&h->Pt, (size_t)ix.m_pad * d));
   TTRY(h->dalloc(&h->normP, (size_t)ix.m_pad));
   TTRY(h->dalloc(&h->Prow, (size_t)m * d));
+  TTRY(h->dalloc(&h->Qrow, (size_t)n * d));
   if (ix.bf16) {
     TTRY(h->dalloc(&h->Qb, (size_t)ix.n_pad * ix.d16));
     TTRY(h->dalloc(&h->Pb, (size_t)ix.m_pad * ix.d16));
   }
-  launch_tile_rows(Qd, h->permQ, h->s2Q, n, ix.n_pad, d, ix.d16, h->Qt, h->normQ, h->Qb, nullptr, s);
+  launch_tile_rows(Qd, h->permQ, h->s2Q, n, ix.n_pad, d, ix.d16, h->Qt, h->normQ, h->Qb, h->Qrow, s);
   launch_tile_rows(Pd, h->permP, h->s2P, m, ix.m_pad, d, ix.d16, h->Pt, h->normP, h->Pb, h->Prow, s);
   TTRY(hipGetLastError());
   TTRY(hipStreamSynchronize(s));
   free_tmp();
-  ix.Qt = h->Qt; ix.Qb = h->Qb; ix.normQ = h->normQ; ix.permQ = h->permQ;
+  ix.Qt = h->Qt; ix.Qrow = h->Qrow; ix.Qb = h->Qb; ix.normQ = h->normQ; ix.permQ = h->permQ;
   ix.Pt = h->Pt; ix.Pb = h->Pb; ix.Prow = h->Prow; ix.normP = h->normP;
 
   // Steps 2-3: lower-bound arrays and blocks.
@@ -490,7 +491,7 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
   b.qcap = 0;
   HIPTRY(h->dalloc(&b.qn, chunk));
   HIPTRY(h->dalloc(&b.perm, chunk));
-  HIPTRY(h->dalloc(&b.qt, cp * ix.d));
+  HIPTRY(h->dalloc(&b.qt, cp * (ix.d + (ix.d & 1))));
   if (ix.bf16) HIPTRY(h->dalloc(&b.qb, cp * ix.d16));
   HIPTRY(h->dalloc(&b.qn_s, cp));
   HIPTRY(h->dalloc(&b.k_s, cp));
@@ -539,7 +540,8 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
   launch_set_i64(offs, 0, s);
   HIPTRY(hipGetLastError());
   if (nq == 0) return RK_OK;
-  if (bfilter_lds_bytes(ix) > kMaxLds) {
+  const size_t tile_bytes = ix.bf16 ? (size_t)ix.d16 * TILE * 2 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
+  if (bfilter_lds_bytes(ix) > kMaxLds || tile_bytes > bfilter_max_tile_bytes()) {
     // too wide for the block-resident batched filter: one query at a time
     for (int64_t i = 0; i < nq; ++i) {
       rk_status st = enqueue_query(h, qs_dev + i * ix.d, ks[i], ids, cap, offs + i, offs + i + 1,
@@ -840,7 +842,7 @@ int64_t rk_index_footprint(int64_t n, int64_t m, int32_t d, int32_t k_max, const
   const int64_t d16 = round_up(d, 16);
   int64_t b = 0;
   b += n * 8 + m * 8 + n * 4 + m * 4;                 // squared norms, permutations
-  b += np * d * 4 + np * 4 + mp * d * 4 + mp * 4 + m * d * 4;  // tiled copies, norms, rows
+  b += np * d * 4 + np * 4 + mp * d * 4 + mp * 4 + m * d * 4 + n * d * 4;  // tiled copies, norms, rows
   if (o.precision == RK_BF16) b += (np + mp) * d16 * 2;
   b += (int64_t)k_max * np * 12 + (int64_t)k_max * nB * 4 + nB * 4;  // L64, L32, LB, bnorm
   b += ((n + 31) / 32) * 4 + np * 12 + 4 * 4 + 4 + 16 * 8 + d * 4 + std::max<int64_t>(n, 1) * 4 + 8;
