@@ -101,7 +101,12 @@ def test_null_pointers_rejected():
 
 
 def test_footprint_model():
-    fp32 = rkmips.index_footprint(100_000, 20_000, 50, 25)
-    bf16 = rkmips.index_footprint(100_000, 20_000, 50, 25, precision="bf16")
-    assert 30e6 < fp32 < 80e6 and bf16 > fp32
+    n, m, d, kmax = 100_000, 20_000, 50, 25
+    fp32 = rkmips.index_footprint(n, m, d, kmax)
+    bf16 = rkmips.index_footprint(n, m, d, kmax, precision="bf16")
+    # dominant arrays: users tiled + row-major (2 n d 4), items tiled + row-major
+    # (2 m d 4), bound tables L64 + L32 (kmax n 12)
+    core = 2 * n * d * 4 + 2 * m * d * 4 + kmax * n * 12
+    assert core < fp32 < 1.25 * core
+    assert bf16 - fp32 >= (n + m) * 64 * 2  # bf16 copies, d padded to 64
     assert rkmips.index_footprint(-1, 1, 1, 1) == -1
