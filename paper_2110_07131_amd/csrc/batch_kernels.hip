@@ -326,6 +326,9 @@ __global__ void __launch_bounds__(256, 2) k_bfilter(DevIndex ix, BatchView bv) {
   int32_t pf_k = 0;
   const u32x4* qsrc = BF16 ? (const u32x4*)bv.qb : (const u32x4*)bv.qt;
 
+  // bounded table: this wave's current pair chunk and its fill
+  int ccur = -1, cfill_w = kPairChunk;
+
   int T = next_live(masks, 0, nT);
   if (T < nT) {
     stage_tile(qsrc, bv, T, tile_vecs, t, pf, pf_n, pf_k);
@@ -432,7 +435,10 @@ __global__ void __launch_bounds__(256, 2) k_bfilter(DevIndex ix, BatchView bv) {
       atomicOr(&bv.bits[(int64_t)jo * bv.W + (orig_u >> 5)], 1u << (orig_u & 31));
       atomicAdd(&bv.counts[jo], 1ull);
     }
-    // ---- undecided pairs: appended (one atomic per wave)
+    // ---- undecided pairs: appended (one atomic per wave).  Exact table:
+    // one flat list.  Bounded table: the wave fills chunks of its own, each
+    // registered in the block's chunk list, so that the scan finds the
+    // block's pairs together.
     if (__ballot(und != 0u)) {
       const int cnt = __popc(und);
       int incl = cnt;
@@ -440,22 +446,67 @@ __global__ void __launch_bounds__(256, 2) k_bfilter(DevIndex ix, BatchView bv) {
         const int v = __shfl_up(incl, off);
         if (lane >= off) incl += v;
       }
-      int base = 0;
-      if (lane == 63) base = atomicAdd(bv.npairs, incl);
-      base = __shfl(base, 63);
-      int pos = base + incl - cnt;
       uint32_t ovf = 0;  // pairs beyond the list's capacity
+      if (ix.exact) {
+        int base = 0;
+        if (lane == 63) base = atomicAdd(bv.npairs, incl);
+        base = __shfl(base, 63);
+        int pos = base + incl - cnt;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        if ((und >> r) & 1u) {
-          if (pos < bv.pair_cap) {
-            bv.pair_u[pos] = (int32_t)u;
-            bv.pair_j[pos] = (int32_t)((int64_t)T * TILE + quarter_row(qhalf, half, r));
-            bv.pair_s[pos] = acc[r];
-          } else {
-            ovf |= 1u << r;
+        for (int r = 0; r < 16; ++r) {
+          if ((und >> r) & 1u) {
+            if (pos < bv.pair_cap) {
+              bv.pair_u[pos] = (int32_t)u;
+              bv.pair_j[pos] = (int32_t)((int64_t)T * TILE + quarter_row(qhalf, half, r));
+              bv.pair_s[pos] = acc[r];
+            } else {
+              ovf |= 1u << r;
+            }
+            ++pos;
           }
-          ++pos;
+        }
+      } else {
+        const int total = __shfl(incl, 63);
+        const int avail = kPairChunk - cfill_w;  // free slots of the current chunk
+        const int need = total > avail ? (total - avail + kPairChunk - 1) / kPairChunk : 0;
+        int nb = 0;
+        if (need > 0) {
+          if (lane == 0) nb = atomicAdd(bv.nchunks, need);
+          nb = __shfl(nb, 0);
+          if (lane < need && nb + lane < bv.chunk_cap) {
+            bv.cfill[nb + lane] = kPairChunk;  // the last one is corrected at the end
+            const int at = atomicAdd(&bv.bcnt[B], 1);
+            bv.bchunks[B * bv.maxc + at] = nb + lane;
+          }
+        }
+        int p = incl - cnt;  // this lane's first pair within the wave's append
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          if ((und >> r) & 1u) {
+            int c, slot;
+            if (p < avail) {
+              c = ccur;
+              slot = cfill_w + p;
+            } else {
+              c = nb + (p - avail) / kPairChunk;
+              slot = (p - avail) % kPairChunk;
+            }
+            if (c < bv.chunk_cap) {
+              const int64_t pos = (int64_t)c * kPairChunk + slot;
+              bv.pair_u[pos] = (int32_t)u;
+              bv.pair_j[pos] = (int32_t)((int64_t)T * TILE + quarter_row(qhalf, half, r));
+              bv.pair_s[pos] = acc[r];
+            } else {
+              ovf |= 1u << r;
+            }
+            ++p;
+          }
+        }
+        if (need > 0) {
+          ccur = nb + need - 1;
+          cfill_w = total - avail - (need - 1) * kPairChunk;
+        } else {
+          cfill_w += total;
         }
       }
       while (ovf) {  // rare: decide in float64 here
@@ -480,6 +531,7 @@ __global__ void __launch_bounds__(256, 2) k_bfilter(DevIndex ix, BatchView bv) {
     __syncthreads();
     if (Tn < nT) stage_tile(qsrc, bv, Tn, tile_vecs, t, pf, pf_n, pf_k);
   }
+  if (!ix.exact && lane == 0 && ccur >= 0 && ccur < bv.chunk_cap) bv.cfill[ccur] = cfill_w;
 
   if (bv.ctr) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -530,103 +582,321 @@ __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView b
   if (bv.ctr && yes_count) atomicAdd(&bv.ctr[C_TYES], yes_count);
 }
 
-template <bool BF16>
-__global__ void __launch_bounds__(256) k_bverify(DevIndex ix, BatchView bv) {
-  const int lane = threadIdx.x & 63;
-  const int np = min(*bv.npairs, bv.pair_cap);
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
-  for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < np; w += nwaves) {
-    const int64_t r = bv.pair_u[w];
-    const int32_t jj = bv.pair_j[w];
-    const float s = bv.pair_s[w];
-    const int k = bv.k_s[jj];
-    const float nq = bv.qn_s[jj];
-    const float nu = ix.normQ[r];
-    const float euq = margin(ix, nu, nq);
-    const float sl = s - euq;
-    const int32_t jo0 = bv.perm[jj];
-    // Lemma 2 (certified): items from the k-th on cannot beat q.
-    if (sl >= (ix.cs_inflate * nu) * ix.normP[k - 1]) {
-      if (lane == 0) {
-        set_pair_result(bv, ix, r, jo0);
-        if (bv.ctr) atomicAdd(&bv.ctr[C_L2YES], 1ull);
-      }
-      continue;
-    }
-    int64_t lo = 0, hi = ix.m;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if ((ix.cs_inflate * nu) * ix.normP[mid] <= sl) hi = mid;
-      else lo = mid + 1;
-    }
-    const int64_t stop = lo;
-    int beats = 0, unsure = 0;
-    int64_t scanned = 0;
-    const int64_t ub = r / TILE, ul = r % TILE;
-    for (int64_t t0 = 0; t0 < stop && beats < k; t0 += TILE) {
-      const int64_t j = t0 + lane;
-      const bool inb = j < stop;
-      float g;
-      if (!BF16) {
-        const float* u = ix.Qt + ub * (int64_t)ix.d * TILE + ul;
-        const float* p = ix.Pt + (t0 / TILE) * (int64_t)ix.d * TILE + lane;
-        float x0 = 0.f, x1 = 0.f;
-        int c = 0;
-        for (; c + 2 <= ix.d; c += 2) {
-          x0 = fmaf(u[c * TILE], p[c * TILE], x0);
-          x1 = fmaf(u[(c + 1) * TILE], p[(c + 1) * TILE], x1);
-        }
-        if (c < ix.d) x0 = fmaf(u[c * TILE], p[c * TILE], x0);
-        g = x0 + x1;
-      } else {
-        const int G = ix.d16 / 8;
-        const uint4* u = (const uint4*)(ix.Qb + (ub * G * TILE + ul) * 8);
-        const uint4* p = (const uint4*)(ix.Pb + ((t0 / TILE) * G * TILE + lane) * 8);
-        float x0 = 0.f, x1 = 0.f;
-        for (int gg = 0; gg < G; ++gg) {
-          const uint4 wu = u[gg * TILE], wp = p[gg * TILE];
-          const uint32_t xu[4] = {wu.x, wu.y, wu.z, wu.w}, xp[4] = {wp.x, wp.y, wp.z, wp.w};
+// ---------------------------------------------------------------------------
+// Grouped linear scan (bounded table): Algorithm 2 for every undecided pair of
+// one user block at once.  u.p does not depend on q, so the scan's products
+// are computed once per (user, item) of the block, in 64x64 float32 MFMA tiles
+// over the items in norm order, and each pair reads them through an order
+// statistic: within a prefix of the items at least k items beat q iff the
+// k-th largest u.p of the prefix exceeds f(q,u) (Corollary 2), and once the
+// prefix reaches the pair's Corollary 1 limit (the first item with
+// cs|u||p| <= a lower bound of f(q,u); no later item can beat q) fewer than k
+// beats in it mean "yes".  Each user keeps the k_max largest approximate
+// products of the items scanned so far (LDS).  With e = eps|u||p_0| + eps_abs
+// bounding the error of every product of the prefix and [lo, hi] = s -+ e_q
+// bounding f(q,u):
+//   no   iff  top_k - e > hi;   yes iff  top_k + e <= lo   (top_k = -inf when
+//   the prefix has fewer than k items); otherwise the float64 scan decides.
+// Short pass: the first kShortTiles item tiles, then every pair is read once;
+// most pairs end here.  The others are flagged; the scan then continues, for
+// the users that have such pairs only, up to each user's largest limit, and
+// the flagged pairs are decided at the end.
+constexpr int kShortTiles = 4;
+
+template <int NV>
+__device__ __forceinline__ void load_item_tile(const DevIndex& ix, int64_t I, int t,
+                                               u32x4 (&pf)[NV]) {
+  const u32x4* src = (const u32x4*)(ix.Pt + I * (int64_t)ix.d * TILE);
+  const int nv = ix.d * (TILE / 4);
 #pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            x0 = fmaf(bf16_to_f32((uint16_t)(xu[h] & 0xFFFFu)), bf16_to_f32((uint16_t)(xp[h] & 0xFFFFu)), x0);
-            x1 = fmaf(bf16_to_f32((uint16_t)(xu[h] >> 16)), bf16_to_f32((uint16_t)(xp[h] >> 16)), x1);
+  for (int v = 0; v < NV; ++v) {
+    const int i = v * 256 + t;
+    if (i < nv) pf[v] = src[i];
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void store_item_tile(float* pbuf, int d, int t, const u32x4 (&pf)[NV]) {
+  u32x4* dst = (u32x4*)pbuf;
+  const int nv = d * (TILE / 4);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int i = v * 256 + t;
+    if (i < nv) dst[i] = pf[v];
+  }
+}
+
+// f(q,u) approximated in float32, sequential over the coordinates (query row
+// in caller order, user column of the block tile in LDS).
+__device__ __forceinline__ float dot32_col(const float* __restrict__ q, const float* ucol, int d) {
+  float acc = 0.f;
+  for (int c = 0; c < d; ++c) acc = fmaf(q[c], ucol[c * TILE], acc);
+  return acc;
+}
+
+__device__ __forceinline__ int norm_limit(const DevIndex& ix, float csu, float lo, int from) {
+  // first item i >= from with csu * |p_i| <= lo (items are norm-sorted)
+  int a = from, b = (int)ix.m;
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (csu * ix.normP[mid] <= lo) b = mid;
+    else a = mid + 1;
+  }
+  return a;
+}
+
+// An undecided pair, decided exactly from the user's list of the k_max
+// largest products of the prefix (values and item ids): entries certainly
+// above f(q,u) count, entries within the error band are compared in float64
+// (usually the one item equal to q), and the items outside the list are below
+// its last entry, certainly not above f(q,u) unless that entry is itself in
+// the band, when the float64 scan decides.  The prefix must reach the pair's
+// Corollary 1 limit.
+__device__ __forceinline__ bool resolve_pair(const DevIndex& ix, const BatchView& bv, int64_t u,
+                                          int32_t jj, int k, float lo, float hi, float nu,
+                                          const float* tk, const int32_t* ti, int K) {
+  const float* urow = ix.Qrow + u * ix.d;
+  const float* qrow = bv.qs + (int64_t)bv.perm[jj] * ix.d;
+  double fq = 0.0;
+  bool have_fq = false;
+  int beats = 0;
+  for (int p = 0; p < K; ++p) {
+    const int32_t id = ti[p];
+    if (id < 0) return true;  // the prefix has no further item
+    const float v = tk[p];
+    const float ei = ix.eps_rel32 * (nu * ix.normP[id]) + ix.eps_abs;
+    if (v - ei > hi) {
+      ++beats;
+    } else if (!(v + ei <= lo)) {
+      if (!have_fq) {
+        fq = dot64_rows(qrow, urow, ix.d);
+        have_fq = true;
+      }
+      beats += dot64_rows(ix.Prow + (int64_t)id * ix.d, urow, ix.d) > fq;
+    }
+    if (beats >= k) return false;
+  }
+  const float eK = ix.eps_rel32 * (nu * ix.normP[0]) + ix.eps_abs;
+  if (tk[K - 1] + eK <= lo) return true;
+  return decide_f64(ix, bv, u, jj);
+}
+
+template <int NV>
+__global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
+  const int64_t B = blockIdx.x;
+  const int nch = min(bv.bcnt[B], bv.maxc);
+  if (nch == 0) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  const int uh = wave & 1, ih = wave >> 1;
+  // K = k_max + 2 list entries: the entry after the k-th is usually not the
+  // item equal to q, so an undecided pair rarely needs the float64 scan
+  const int d = ix.d, d2 = d + (d & 1), K = ix.kmax + 2;
+  constexpr int GS = TILE + 1;          // gamma row stride
+  float* ubuf = (float*)lds_raw;        // [d2][64] users of the block
+  float* pbuf = ubuf + d2 * TILE;       // [d2][64] current item tile
+  float* gam = pbuf + d2 * TILE;        // [64][GS] products of the tile
+  float* topk = gam + TILE * GS;        // [64][K] descending
+  int32_t* topi = (int32_t*)(topk + TILE * K);  // [64][K] their item ids (-1: none)
+  int* Tu = topi + TILE * K;            // [64] scan limit per user (long pass)
+  __shared__ int nflag;
+  const int32_t* clist = bv.bchunks + B * bv.maxc;
+
+  {
+    const u32x4* src = (const u32x4*)(ix.Qt + B * (int64_t)d * TILE);
+    u32x4* dst = (u32x4*)ubuf;
+    for (int i = t; i < d * TILE / 4; i += 256) dst[i] = src[i];
+    if (d & 1) {
+      if (t < TILE) ubuf[d * TILE + t] = 0.f;
+      else if (t < 2 * TILE) pbuf[d * TILE + t - TILE] = 0.f;
+    }
+    for (int i = t; i < TILE * K; i += 256) {
+      topk[i] = -INFINITY;
+      topi[i] = -1;
+    }
+    if (t < TILE) Tu[t] = 0;
+    if (t == 0) nflag = 0;
+  }
+  const int nshort = (int)min((int64_t)kShortTiles, (int64_t)ix.mB);
+  unsigned long long c_scan = 0, c_l2 = 0, c_f64 = 0;
+
+  // Item tiles [I0, I1): MFMA quarter (user half uh, item half ih) for the
+  // active users into gamma, then lane u of wave 0 merges its row into the
+  // user's list.  The next tile is prefetched into registers.
+  u32x4 pf[NV];
+  auto scan_tiles = [&](int I0, int I1, bool all_users) {
+    if (I0 >= I1) return;
+    load_item_tile(ix, I0, t, pf);
+    __syncthreads();
+    store_item_tile(pbuf, d, t, pf);
+    if (I0 + 1 < I1) load_item_tile(ix, I0 + 1, t, pf);
+    for (int I = I0; I < I1; ++I) {
+      __syncthreads();  // pbuf holds tile I; gamma is free
+      const int ul = uh * 32 + col;
+      const bool act = all_users || Tu[ul] > I * TILE;
+      if (__ballot(act)) {
+        f32x16 acc = {}, acc2 = {};
+        const float* pf_ = pbuf + ih * 32 + col + half * TILE;
+        const float* uf = ubuf + uh * 32 + col + half * TILE;
+        const int nsteps = d2 / 2;
+        int ks = 0;
+        for (; ks + 4 <= nsteps; ks += 4) {
+          float a[4], b[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            a[i] = pf_[(2 * (ks + i)) * TILE];
+            b[i] = uf[(2 * (ks + i)) * TILE];
+          }
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[0], acc, 0, 0, 0);
+          acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b[1], acc2, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], b[2], acc, 0, 0, 0);
+          acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], b[3], acc2, 0, 0, 0);
+        }
+        for (; ks < nsteps; ++ks)
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pf_[2 * ks * TILE], uf[2 * ks * TILE], acc, 0, 0, 0);
+        acc += acc2;
+        const int64_t left = ix.m - (int64_t)I * TILE;  // items of this tile that exist
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = quarter_row(ih, half, r);
+          gam[ul * GS + row] = row < left ? acc[r] : -INFINITY;
+        }
+      }
+      __syncthreads();  // gamma complete; pbuf free
+      if (I + 1 < I1) {
+        store_item_tile(pbuf, d, t, pf);
+        if (I + 2 < I1) load_item_tile(ix, I + 2, t, pf);
+      }
+      if (t < TILE && (all_users || Tu[t] > I * TILE)) {
+        float* tk = topk + t * K;
+        int32_t* ti = topi + t * K;
+        float th = tk[K - 1];
+        const float* g = gam + t * GS;
+        for (int i = 0; i < TILE; ++i) {
+          const float v = g[i];
+          if (v > th) {
+            int p = K - 1;
+            while (p > 0 && tk[p - 1] < v) {
+              tk[p] = tk[p - 1];
+              ti[p] = ti[p - 1];
+              --p;
+            }
+            tk[p] = v;
+            ti[p] = I * TILE + i;
+            th = tk[K - 1];
           }
         }
-        g = x0 + x1;
+        if (bv.ctr) {
+          const int64_t left = ix.m - (int64_t)I * TILE;
+          c_scan += (unsigned long long)(left < TILE ? left : TILE);
+        }
       }
-      const float np_ = inb ? ix.normP[j] : 0.f;
-      const float tol = margin(ix, nu, np_) + euq;
-      const float diff = g - s;
-      const bool beat = inb && (diff > tol);
-      const bool unc = inb && !beat && !(diff <= -tol);
-      beats += __popcll(__ballot(beat));
-      unsure += __popcll(__ballot(unc));
-      scanned += (stop - t0 < TILE) ? (stop - t0) : TILE;
     }
-    if (bv.ctr && lane == 0) atomicAdd(&bv.ctr[C_SCAN], (unsigned long long)scanned);
-    const int32_t jo = jo0;
-    if (beats >= k) continue;
-    if (beats + unsure < k) {
-      if (lane == 0) set_pair_result(bv, ix, r, jo);
-      continue;
-    }
-    // float64 scan in this wave: lane = item, counts up to k
-    const float* u = ix.Qrow + r * ix.d;
-    const double fq = dot64_rows(bv.qs + (int64_t)jo * ix.d, u, ix.d);
-    const double csu = (double)ix.cs_inflate * (double)nu * (1.0 + 0x1p-50);
-    int b64 = 0;
-    for (int64_t t0 = 0; t0 < ix.m && b64 < k; t0 += TILE) {
-      const int64_t j = t0 + lane;
-      bool beat = false;
-      if (j < ix.m && csu * (double)ix.normP[j] > fq) {
-        beat = dot64_rows(ix.Prow + j * ix.d, u, ix.d) > fq;
+    __syncthreads();
+  };
+
+  scan_tiles(0, nshort, true);
+  const int64_t S0 = (int64_t)nshort * TILE;  // items covered by the short pass
+  const float e0 = ix.eps_rel32 * ix.normP[0];  // times |u|, plus eps_abs: any product's bound
+
+  // f(q,u) in [lo, hi]: float32 bounds (recomputed from the float32 rows in
+  // bf16 mode, where the filter's product is a bf16 one).
+  auto pair_bounds = [&](int64_t slot, int ul, int32_t jj, float nu, float& lo, float& hi) {
+    float s = bv.pair_s[slot];
+    if (ix.bf16) s = dot32_col(bv.qs + (int64_t)bv.perm[jj] * d, ubuf + ul, d);
+    const float es = ix.eps_rel32 * (nu * bv.qn_s[jj]) + ix.eps_abs;
+    lo = s - es;
+    hi = s + es;
+  };
+
+  // Pass 1: every pair.  0 no, 1 yes, 2 long (flagged), 3 resolve.
+  for (int ci = 0; ci < nch; ++ci) {
+    const int32_t c = clist[ci];
+    if (t >= bv.cfill[c]) continue;
+    const int64_t slot = (int64_t)c * kPairChunk + t;
+    const int64_t u = bv.pair_u[slot];
+    const int ul = (int)(u - B * TILE);
+    const int32_t jj = bv.pair_j[slot];
+    const int k = bv.k_s[jj];
+    const float nu = ix.normQ[u];
+    const float e = e0 * nu + ix.eps_abs;
+    const float kth = topk[ul * K + k - 1];
+    int cls;
+    float lo = 0.f, hi = 0.f;
+    const float sb = bv.pair_s[slot];
+    const float eb = ix.eps_rel * (nu * bv.qn_s[jj]) + ix.eps_abs;  // bulk-precision bound
+    if (kth - e > sb + eb) {
+      cls = 0;
+    } else {
+      pair_bounds(slot, ul, jj, nu, lo, hi);
+      const float csu = ix.cs_inflate * nu;
+      if (kth - e > hi) {
+        cls = 0;
+      } else if (lo >= csu * ix.normP[k - 1]) {
+        cls = 1;  // Lemma 2
+        ++c_l2;
+      } else if (S0 >= ix.m || csu * ix.normP[S0] <= lo) {
+        cls = (kth + e <= lo) ? 1 : 3;
+      } else {
+        cls = 2;
+        atomicMax(&Tu[ul], norm_limit(ix, csu, lo, (int)S0));
       }
-      b64 += __popcll(__ballot(beat));
-      // items are norm-sorted: once a whole tile is past the bound, stop
-      if (__ballot(j < ix.m && csu * (double)ix.normP[j] > fq) == 0ull) break;
     }
-    if (bv.ctr && lane == 0) atomicAdd(&bv.ctr[C_RCHK], 1ull);
-    if (b64 < k && lane == 0) set_pair_result(bv, ix, r, jo);
+    bv.pair_st[slot] = cls == 2;
+    if (cls == 2) atomicAdd(&nflag, 1);
+    bool yes = cls == 1;
+    if (cls == 3) {
+      yes = resolve_pair(ix, bv, u, jj, k, lo, hi, nu, topk + ul * K, topi + ul * K, K);
+      ++c_f64;
+    }
+    if (yes) set_pair_result(bv, ix, u, bv.perm[jj]);
+  }
+  __syncthreads();
+
+  // Long pass: flagged pairs, their users' scan continued to each user's limit.
+  if (nflag > 0) {
+    int tmax = 0;
+    for (int i = 0; i < TILE; ++i) tmax = max(tmax, Tu[i]);
+    scan_tiles(nshort, (int)((tmax + TILE - 1) / TILE), false);
+    for (int ci = 0; ci < nch; ++ci) {
+      const int32_t c = clist[ci];
+      if (t >= bv.cfill[c]) continue;
+      const int64_t slot = (int64_t)c * kPairChunk + t;
+      if (!bv.pair_st[slot]) continue;
+      const int64_t u = bv.pair_u[slot];
+      const int ul = (int)(u - B * TILE);
+      const int32_t jj = bv.pair_j[slot];
+      const int k = bv.k_s[jj];
+      const float nu = ix.normQ[u];
+      const float e = e0 * nu + ix.eps_abs;
+      const float kth = topk[ul * K + k - 1];
+      float lo, hi;
+      pair_bounds(slot, ul, jj, nu, lo, hi);
+      bool yes;
+      if (kth - e > hi) {
+        yes = false;
+      } else if (kth + e <= lo) {
+        yes = true;
+      } else {
+        yes = resolve_pair(ix, bv, u, jj, k, lo, hi, nu, topk + ul * K, topi + ul * K, K);
+        ++c_f64;
+      }
+      if (yes) set_pair_result(bv, ix, u, bv.perm[jj]);
+    }
+  }
+
+  if (bv.ctr) {
+    for (int off = 32; off > 0; off >>= 1) {
+      c_l2 += __shfl_xor(c_l2, off);
+      c_f64 += __shfl_xor(c_f64, off);
+      c_scan += __shfl_xor(c_scan, off);
+    }
+    if (lane == 0) {
+      if (c_l2) atomicAdd(&bv.ctr[C_L2YES], c_l2);
+      if (c_f64) atomicAdd(&bv.ctr[C_RCHK], c_f64);
+      if (c_scan) atomicAdd(&bv.ctr[C_SCAN], c_scan);
+    }
   }
 }
 
@@ -707,11 +977,21 @@ __global__ void __launch_bounds__(256) k_bassemble(BatchView bv, const int64_t* 
   }
 }
 
+// Bounded table: empty chunk lists before the filter.
+__global__ void k_bclear(int32_t* __restrict__ bcnt, int32_t nB, int32_t* __restrict__ nchunks) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nB) bcnt[i] = 0;
+  if (i == 0) *nchunks = 0;
+}
+
 // ---------------------------------------------------------------------------
 void launch_bprep(const DevIndex& ix, const BatchView& bv, const int32_t* ks_dev, int32_t nq,
                   hipStream_t s) {
   hipLaunchKernelGGL(k_bnorms, dim3((nq + 3) / 4), dim3(256), 0, s, bv.qs, nq, ix.d, bv.qn,
                      bv.npairs);
+  if (!ix.exact && ix.nB > 0)
+    hipLaunchKernelGGL(k_bclear, dim3((ix.nB + 255) / 256), dim3(256), 0, s, bv.bcnt, ix.nB,
+                       bv.nchunks);
   hipLaunchKernelGGL(k_bsort, dim3(1), dim3(1024), 0, s, bv.qn, ks_dev, nq, bv.perm);
   dim3 blk(64, 4);
   hipLaunchKernelGGL(k_btile, dim3((bv.nq_pad + 3) / 4), blk, 0, s, bv.qs, ks_dev, bv.qn,
@@ -753,15 +1033,31 @@ void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
   else bfilter_prec<false>(ix, bv, lds, s);
 }
 
+size_t bscan_lds_bytes(const DevIndex& ix) {
+  const size_t d2 = (size_t)(ix.d + (ix.d & 1));
+  return (2 * d2 * TILE + TILE * (TILE + 1) + 2 * (size_t)TILE * (ix.kmax + 2) + TILE) * 4;
+}
+
+template <int NV>
+static void bscan_nv(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
+  const size_t lds = bscan_lds_bytes(ix);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_bscan<NV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  hipLaunchKernelGGL((k_bscan<NV>), dim3(ix.nB), dim3(256), lds, s, ix, bv);
+}
+
 void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
   if (ix.nB == 0) return;
   if (ix.exact) {
     hipLaunchKernelGGL(k_brecheck_exact, dim3(256), dim3(256), 0, s, ix, bv);
-  } else if (ix.bf16) {
-    hipLaunchKernelGGL(k_bverify<true>, dim3(2048), dim3(256), 0, s, ix, bv);
-  } else {
-    hipLaunchKernelGGL(k_bverify<false>, dim3(2048), dim3(256), 0, s, ix, bv);
+    return;
   }
+  const int per_thread = (ix.d * (TILE / 4) + 255) / 256;  // 16-byte vectors of an item tile
+  if (per_thread <= 2) bscan_nv<2>(ix, bv, s);
+  else if (per_thread <= 4) bscan_nv<4>(ix, bv, s);
+  else if (per_thread <= 8) bscan_nv<8>(ix, bv, s);
+  else bscan_nv<16>(ix, bv, s);
 }
 
 void launch_bassemble(const BatchView& bv, int32_t nq, const int64_t* base, int64_t* offs,

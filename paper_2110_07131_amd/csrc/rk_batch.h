@@ -5,6 +5,7 @@
 namespace rk {
 
 constexpr int kBatchChunkMax = 4096;  // queries per chunk (single-workgroup sort in LDS)
+constexpr int kPairChunk = 256;       // slots per pair chunk (bounded table)
 
 struct BatchView {
   const float* qs;              // chunk queries [nq][d], caller order
@@ -25,6 +26,15 @@ struct BatchView {
   int32_t* pair_u;              // sorted user index
   int32_t* pair_j;              // sorted query position
   float* pair_s;                // bulk-precision u.q
+  // Bounded table only: the pair slots are grouped in chunks of kPairChunk;
+  // every chunk holds pairs of one user block, listed per block.
+  int32_t* pair_st;             // 1 = left for the scan's long pass
+  int32_t* cfill;               // [chunk_cap] used slots per chunk
+  int32_t* nchunks;             // chunks handed out (may exceed chunk_cap)
+  int32_t chunk_cap;
+  int32_t maxc;                 // list capacity per block
+  int32_t* bcnt;                // [nB] chunks of the filter's pairs per block
+  int32_t* bchunks;             // [nB][maxc] their ids
   unsigned long long* ctr;      // statistics or nullptr
 };
 
@@ -34,6 +44,8 @@ size_t bfilter_lds_bytes(const DevIndex& ix);
 size_t bfilter_max_tile_bytes();
 void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s);
+// Dynamic LDS of the grouped linear scan (bounded table).
+size_t bscan_lds_bytes(const DevIndex& ix);
 // offs[0] must hold the chunk's first offset; writes offs[1..nq] and ids.
 void launch_bassemble(const BatchView& bv, int32_t nq, const int64_t* base, int64_t* offs,
                       int32_t* ids, int64_t cap, hipStream_t s);

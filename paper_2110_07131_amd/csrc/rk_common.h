@@ -79,6 +79,7 @@ struct DevIndex {
   float eps_rel;         // relative bound on |approx u.x - f(x,u)| / (|u||x|)
   float eps_abs;         // absolute slack (underflow)
   float cs_inflate;      // 1 + gamma64_d + slack: f(p,u) <= cs_inflate*|u|^*|p|^
+  float eps_rel32;       // eps_rel of float32 products (the verification pass)
 };
 
 // f(x, y) in float64, index order, from two contiguous float32 rows: the

@@ -95,6 +95,10 @@ struct rk_index {
     uint16_t* qb = nullptr;
     int32_t *perm = nullptr, *k_s = nullptr, *npairs = nullptr, *pair_u = nullptr,
             *pair_j = nullptr, *ks_dev = nullptr;
+    // bounded table: chunked pair slots, per-block chunk lists
+    int32_t *pair_st = nullptr, *cfill = nullptr, *nchunks = nullptr, *bcnt = nullptr,
+            *bchunks = nullptr;
+    int32_t chunk_cap = 0, maxc = 0;
     uint32_t* bits = nullptr;
     unsigned long long* counts = nullptr;
     uint8_t* all = nullptr;
@@ -285,6 +289,7 @@ rk_status build_impl(const float* Q, int64_t n, const float* P, int64_t m, int32
   h->eps32 = std::max(eps_fp32(d), o.margin_rel);
   const double eps = std::max(ix.bf16 ? eps_bf16(d) : eps_fp32(d), o.margin_rel);
   ix.eps_rel = f32_up(eps);
+  ix.eps_rel32 = f32_up(h->eps32);
   ix.eps_abs = std::ldexp((double)(d + 2), -124);
   ix.cs_inflate = f32_up(1.0 + gamma_(d, 0x1p-53) + 8 * 0x1p-24);
 
@@ -482,8 +487,11 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
   HIPTRY(hipStreamSynchronize(h->stream));
   for (void* p : {(void*)b.qn, (void*)b.qt, (void*)b.qn_s, (void*)b.pair_s, (void*)b.qb,
                   (void*)b.perm, (void*)b.k_s, (void*)b.npairs, (void*)b.pair_u, (void*)b.pair_j,
-                  (void*)b.ks_dev, (void*)b.bits, (void*)b.counts, (void*)b.all})
+                  (void*)b.ks_dev, (void*)b.bits, (void*)b.counts, (void*)b.all,
+                  (void*)b.pair_st, (void*)b.cfill, (void*)b.nchunks, (void*)b.bcnt,
+                  (void*)b.bchunks})
     if (p) h->dfree(p);
+  b.pair_st = b.cfill = b.nchunks = b.bcnt = b.bchunks = nullptr;
   const DevIndex& ix = h->ix;
   const int64_t cp = round_up(chunk, TILE), W = (ix.n + 31) / 32;
   int64_t pc = std::min<int64_t>((int64_t)chunk * std::max<int64_t>(ix.n_pad, 1), kPairBudget);
@@ -503,6 +511,17 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
   HIPTRY(h->dalloc(&b.pair_j, pc));
   HIPTRY(h->dalloc(&b.pair_s, pc));
   HIPTRY(h->dalloc(&b.ks_dev, chunk));
+  if (!ix.exact) {
+    // Chunks of kPairChunk slots; a block's chunks are all full but the one
+    // each of its four filter waves is filling: at most 64 * cp / kPairChunk + 4.
+    b.chunk_cap = (int32_t)std::min<int64_t>(pc / kPairChunk, INT32_MAX);
+    b.maxc = (int32_t)(TILE * cp / kPairChunk + 4);
+    HIPTRY(h->dalloc(&b.pair_st, std::max<int64_t>(pc, 1)));
+    HIPTRY(h->dalloc(&b.cfill, std::max<int64_t>(b.chunk_cap, 1)));
+    HIPTRY(h->dalloc(&b.nchunks, 1));
+    HIPTRY(h->dalloc(&b.bcnt, std::max<int64_t>(ix.nB, 1)));
+    HIPTRY(h->dalloc(&b.bchunks, (int64_t)std::max<int64_t>(ix.nB, 1) * b.maxc));
+  }
   HIPTRY(hipMemsetAsync(b.bits, 0, (size_t)chunk * std::max<int64_t>(W, 1) * 4, h->stream));
   HIPTRY(hipMemsetAsync(b.counts, 0, (size_t)chunk * 8, h->stream));
   HIPTRY(hipStreamSynchronize(h->stream));
@@ -541,7 +560,8 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
   HIPTRY(hipGetLastError());
   if (nq == 0) return RK_OK;
   const size_t tile_bytes = ix.bf16 ? (size_t)ix.d16 * TILE * 2 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
-  if (bfilter_lds_bytes(ix) > kMaxLds || tile_bytes > bfilter_max_tile_bytes()) {
+  if (bfilter_lds_bytes(ix) > kMaxLds || tile_bytes > bfilter_max_tile_bytes() ||
+      (!ix.exact && bscan_lds_bytes(ix) > kMaxLds)) {
     // too wide for the block-resident batched filter: one query at a time
     for (int64_t i = 0; i < nq; ++i) {
       rk_status st = enqueue_query(h, qs_dev + i * ix.d, ks[i], ids, cap, offs + i, offs + i + 1,
@@ -566,6 +586,8 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
     bv.bits = b.bits; bv.W = W; bv.counts = b.counts; bv.all = b.all; bv.n = ix.n;
     bv.npairs = b.npairs; bv.pair_cap = (int32_t)b.pair_cap;
     bv.pair_u = b.pair_u; bv.pair_j = b.pair_j; bv.pair_s = b.pair_s;
+    bv.pair_st = b.pair_st; bv.cfill = b.cfill; bv.nchunks = b.nchunks;
+    bv.chunk_cap = b.chunk_cap; bv.maxc = b.maxc; bv.bcnt = b.bcnt; bv.bchunks = b.bchunks;
     bv.ctr = h->counting ? h->ctr_dev : nullptr;
     { Timer t(h, s, K_BPREP); launch_bprep(ix, bv, b.ks_dev, nc, s); }
     { Timer t(h, s, K_BFILTER); launch_bfilter(ix, bv, s); }

@@ -106,3 +106,64 @@ def test_batch_counters_and_device_api():
     assert st["blocks_visited"] == len(ks) * st["n_blocks"]
     assert st["users_evaluated"] + 0 >= st["lemma1_no"] + st["table_yes"]
     idx.free()
+
+
+# --- grouped linear scan (bounded table) -----------------------------------
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_grouped_scan_long_pass(prec):
+    # m = 1000 items (16 tiles): members need scans well past the short pass
+    w = datagen.config_workload("parity")
+    rng = np.random.default_rng(21)
+    qs = np.ascontiguousarray(np.vstack([w.queries, w.P[rng.integers(0, len(w.P), 40)]]))
+    ks = rng.integers(1, 11, len(qs)).astype(np.int32)
+    ks[:5] = 10
+    idx = Index.build(w.Q, w.P, 10, lb_items=20, precision=prec)
+    idx.set_counting(True)
+    off, ids = idx.reverse_kmips_batch(qs, ks)
+    check_csr(w.Q, w.P, qs, ks, off, ids)
+    st = idx.stats()
+    # the scan evaluated products beyond the 256 items of the short pass
+    assert st["scan_items"] > 256 * 64
+    assert st["results"] == off[-1]
+    idx.free()
+
+
+@pytest.mark.parametrize("cap", [256, 700, 256 * 30])
+def test_grouped_scan_chunk_pool_partly_full(cap):
+    # pairs beyond the chunk pool are decided in float64 by the filter; the
+    # chunks that fit go through the grouped scan
+    w = datagen.workload(700, 400, 16, 0.5, 30, seed=5)
+    rng = np.random.default_rng(5)
+    ks = rng.integers(1, 9, len(w.qidx)).astype(np.int32)
+    idx = Index.build(w.Q, w.P, 8, lb_items=16, pair_cap=cap)
+    off, ids = idx.reverse_kmips_batch(w.queries, ks)
+    check_csr(w.Q, w.P, w.queries, ks, off, ids)
+    idx.free()
+
+
+def test_grouped_scan_several_chunks_bounded():
+    # the per-block chunk lists are emptied between query chunks
+    w = datagen.workload(300, 150, 12, 0.6, 150, seed=13)
+    rng = np.random.default_rng(13)
+    pick = rng.integers(0, 150, 4300)
+    qs = np.ascontiguousarray(w.P[pick])
+    ks = rng.integers(1, 9, len(qs)).astype(np.int32)
+    idx = Index.build(w.Q, w.P, 8, lb_items=10)
+    off, ids = idx.reverse_kmips_batch(qs, ks)
+    for i in list(range(0, 4300, 41)) + [4095, 4096, 4299]:
+        assert np.array_equal(ids[off[i]:off[i + 1]], oracle.brute(w.Q, w.P, qs[i], int(ks[i]))), i
+    idx.free()
+
+
+@pytest.mark.parametrize("m", [30, 256, 257])
+def test_grouped_scan_short_catalog(m):
+    # catalogs within or just past the short pass
+    w = datagen.workload(400, m, 9, 0.8, 20, seed=m)
+    rng = np.random.default_rng(m)
+    qs = np.vstack([w.queries, datagen.vectors(5, 9, 0.8, rng)])
+    ks = rng.integers(1, 7, len(qs)).astype(np.int32)
+    idx = Index.build(w.Q, w.P, 6, lb_items=7)
+    off, ids = idx.reverse_kmips_batch(qs, ks)
+    check_csr(w.Q, w.P, qs, ks, off, ids)
+    idx.free()
