@@ -205,7 +205,8 @@ def main():
         "kernel_time_per_step": kernel_share,
         "counters_per_step": {k: st[k] for k in ("blocks_visited", "blocks_pruned", "users_evaluated",
                                                  "lemma1_no", "lemma2_yes", "table_yes", "survivors",
-                                                 "scan_items", "rechecks", "results")},
+                                                 "scan_items", "rechecks", "results", "scan_long",
+                                                 "scan_full_f64")},
         "build_ms": st0["build_ms"], "index_bytes": st0["footprint_bytes"],
         "cpu_baseline": cpu,
     }

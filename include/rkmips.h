@@ -103,7 +103,10 @@ typedef struct {
     int64_t scan_items;        /* item inner products computed in scans */
     int64_t rechecks;          /* users decided by float64 recomputation */
     int64_t results;           /* total result-set sizes */
-    int64_t reserved[8];
+    int64_t scan_long;         /* batched scan: pairs whose Corollary 1 limit lies
+                                  beyond the short pass (decided by the long pass) */
+    int64_t scan_full_f64;     /* pairs decided by the full float64 scan */
+    int64_t reserved[6];
 } rk_stats;
 
 /* Index fields readable with rk_index_export (sorted = descending norm). */

@@ -602,6 +602,10 @@ __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView b
 // the users that have such pairs only, up to each user's largest limit, and
 // the flagged pairs are decided at the end.
 constexpr int kShortTiles = 4;
+constexpr int kFlagCap = 1024;  // flagged pairs listed in LDS per block
+
+// List length per user: k_max + 2 rounded up to a multiple of 4.
+__host__ __device__ inline int bscan_list_len(int kmax) { return (kmax + 2 + 3) / 4 * 4; }
 
 template <int NV>
 __device__ __forceinline__ void load_item_tile(const DevIndex& ix, int64_t I, int t,
@@ -654,7 +658,8 @@ __device__ __forceinline__ int norm_limit(const DevIndex& ix, float csu, float l
 // Corollary 1 limit.
 __device__ __forceinline__ bool resolve_pair(const DevIndex& ix, const BatchView& bv, int64_t u,
                                           int32_t jj, int k, float lo, float hi, float nu,
-                                          const float* tk, const int32_t* ti, int K) {
+                                          const float* tk, const int32_t* ti, int K,
+                                          unsigned long long& full_scans) {
   const float* urow = ix.Qrow + u * ix.d;
   const float* qrow = bv.qs + (int64_t)bv.perm[jj] * ix.d;
   double fq = 0.0;
@@ -678,6 +683,7 @@ __device__ __forceinline__ bool resolve_pair(const DevIndex& ix, const BatchView
   }
   const float eK = ix.eps_rel32 * (nu * ix.normP[0]) + ix.eps_abs;
   if (tk[K - 1] + eK <= lo) return true;
+  ++full_scans;
   return decide_f64(ix, bv, u, jj);
 }
 
@@ -690,17 +696,21 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int half = lane >> 5, col = lane & 31;
   const int uh = wave & 1, ih = wave >> 1;
-  // K = k_max + 2 list entries: the entry after the k-th is usually not the
-  // item equal to q, so an undecided pair rarely needs the float64 scan
-  const int d = ix.d, d2 = d + (d & 1), K = ix.kmax + 2;
-  constexpr int GS = TILE + 1;          // gamma row stride
+  // K >= k_max + 2 list entries (a multiple of 4): the entry after the k-th
+  // is usually not the item equal to q, so an undecided pair rarely needs
+  // the float64 scan
+  const int d = ix.d, d2 = d + (d & 1), K = bscan_list_len(ix.kmax);
   float* ubuf = (float*)lds_raw;        // [d2][64] users of the block
   float* pbuf = ubuf + d2 * TILE;       // [d2][64] current item tile
-  float* gam = pbuf + d2 * TILE;        // [64][GS] products of the tile
-  float* topk = gam + TILE * GS;        // [64][K] descending
+  float* cand = pbuf + d2 * TILE;       // [64][64] candidates of the tile per user
+  float* topk = cand + TILE * TILE;     // [64][K] list values (sorted after each pass)
   int32_t* topi = (int32_t*)(topk + TILE * K);  // [64][K] their item ids (-1: none)
-  int* Tu = topi + TILE * K;            // [64] scan limit per user (long pass)
+  float* thr = (float*)(topi + TILE * K);       // [64] smallest list value
+  int* ccnt = (int*)(thr + TILE);       // [64] candidates per user
+  int* Tu = ccnt + TILE;                // [64] scan limit per user (long pass)
+  uint8_t* crow = (uint8_t*)(Tu + TILE);  // [64][64] candidate rows within the tile
   __shared__ int nflag;
+  __shared__ int32_t flist[kFlagCap];  // slots of the flagged pairs
   const int32_t* clist = bv.bchunks + B * bv.maxc;
 
   {
@@ -715,15 +725,23 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
       topk[i] = -INFINITY;
       topi[i] = -1;
     }
-    if (t < TILE) Tu[t] = 0;
+    if (t < TILE) {
+      thr[t] = -INFINITY;
+      ccnt[t] = 0;
+      Tu[t] = 0;
+    }
     if (t == 0) nflag = 0;
   }
   const int nshort = (int)min((int64_t)kShortTiles, (int64_t)ix.mB);
-  unsigned long long c_scan = 0, c_l2 = 0, c_f64 = 0;
+  unsigned long long c_scan = 0, c_l2 = 0, c_f64 = 0, c_long = 0, c_full = 0;
+  // list minimum of user t (t < 64) and its position, kept by thread t
+  float mn = -INFINITY;
+  int mp = 0;
 
   // Item tiles [I0, I1): MFMA quarter (user half uh, item half ih) for the
-  // active users into gamma, then lane u of wave 0 merges its row into the
-  // user's list.  The next tile is prefetched into registers.
+  // active users; products above the user's list minimum become candidates;
+  // thread u then puts each candidate in place of its list's minimum.  The
+  // next tile is prefetched into registers.
   u32x4 pf[NV];
   auto scan_tiles = [&](int I0, int I1, bool all_users) {
     if (I0 >= I1) return;
@@ -732,7 +750,7 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
     store_item_tile(pbuf, d, t, pf);
     if (I0 + 1 < I1) load_item_tile(ix, I0 + 1, t, pf);
     for (int I = I0; I < I1; ++I) {
-      __syncthreads();  // pbuf holds tile I; gamma is free
+      __syncthreads();  // pbuf holds tile I; candidate lists are empty
       const int ul = uh * 32 + col;
       const bool act = all_users || Tu[ul] > I * TILE;
       if (__ballot(act)) {
@@ -756,44 +774,101 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
         for (; ks < nsteps; ++ks)
           acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pf_[2 * ks * TILE], uf[2 * ks * TILE], acc, 0, 0, 0);
         acc += acc2;
-        const int64_t left = ix.m - (int64_t)I * TILE;  // items of this tile that exist
+        if (act) {
+          const int64_t left = ix.m - (int64_t)I * TILE;  // items of this tile that exist
+          const float th = thr[ul];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = quarter_row(ih, half, r);
-          gam[ul * GS + row] = row < left ? acc[r] : -INFINITY;
+          for (int r = 0; r < 16; ++r) {
+            const int row = quarter_row(ih, half, r);
+            if (row < left && acc[r] > th) {
+              const int at = atomicAdd(&ccnt[ul], 1);
+              cand[ul * TILE + at] = acc[r];
+              crow[ul * TILE + at] = (uint8_t)row;
+            }
+          }
         }
       }
-      __syncthreads();  // gamma complete; pbuf free
+      __syncthreads();  // candidates complete; pbuf free
       if (I + 1 < I1) {
         store_item_tile(pbuf, d, t, pf);
         if (I + 2 < I1) load_item_tile(ix, I + 2, t, pf);
       }
-      if (t < TILE && (all_users || Tu[t] > I * TILE)) {
-        float* tk = topk + t * K;
-        int32_t* ti = topi + t * K;
-        float th = tk[K - 1];
-        const float* g = gam + t * GS;
-        for (int i = 0; i < TILE; ++i) {
-          const float v = g[i];
-          if (v > th) {
-            int p = K - 1;
-            while (p > 0 && tk[p - 1] < v) {
-              tk[p] = tk[p - 1];
-              ti[p] = ti[p - 1];
-              --p;
+      if (t < TILE) {
+        const int c = ccnt[t];
+        if (c > 0) {
+          float* tk = topk + t * K;
+          int32_t* ti = topi + t * K;
+          for (int i = 0; i < c; ++i) {
+            const float v = cand[t * TILE + i];
+            if (v > mn) {
+              tk[mp] = v;
+              ti[mp] = I * TILE + crow[t * TILE + i];
+              mn = INFINITY;
+              const float4* t4 = (const float4*)tk;
+#pragma unroll 2
+              for (int p = 0; p < K / 4; ++p) {
+                const float4 x = t4[p];
+                if (x.x < mn) mn = x.x, mp = 4 * p;
+                if (x.y < mn) mn = x.y, mp = 4 * p + 1;
+                if (x.z < mn) mn = x.z, mp = 4 * p + 2;
+                if (x.w < mn) mn = x.w, mp = 4 * p + 3;
+              }
             }
-            tk[p] = v;
-            ti[p] = I * TILE + i;
-            th = tk[K - 1];
           }
+          thr[t] = mn;
+          ccnt[t] = 0;
         }
-        if (bv.ctr) {
+        if (bv.ctr && (all_users || Tu[t] > I * TILE)) {
           const int64_t left = ix.m - (int64_t)I * TILE;
           c_scan += (unsigned long long)(left < TILE ? left : TILE);
         }
       }
     }
     __syncthreads();
+    // Sort every list in descending order (value, then item id).
+    if (K <= TILE) {
+      for (int uu = wave; uu < TILE; uu += 4) {
+        float v = lane < K ? topk[uu * K + lane] : -INFINITY;
+        int32_t id = lane < K ? topi[uu * K + lane] : INT32_MAX;
+        for (int size = 2; size <= TILE; size <<= 1) {
+          for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const float ov = __shfl_xor(v, stride);
+            const int32_t oid = __shfl_xor(id, stride);
+            const bool keep_max = ((lane & stride) == 0) == ((lane & size) == 0);
+            const bool other_greater = ov > v || (ov == v && oid < id);
+            const bool other_less = ov < v || (ov == v && oid > id);
+            if (keep_max ? other_greater : other_less) {
+              v = ov;
+              id = oid;
+            }
+          }
+        }
+        if (lane < K) {
+          topk[uu * K + lane] = v;
+          topi[uu * K + lane] = id == INT32_MAX ? -1 : id;
+        }
+      }
+    } else if (t < TILE) {
+      float* tk = topk + t * K;
+      int32_t* ti = topi + t * K;
+      for (int i = 1; i < K; ++i) {
+        const float v = tk[i];
+        const int32_t id = ti[i];
+        int p = i;
+        while (p > 0 && (tk[p - 1] < v || (tk[p - 1] == v && ti[p - 1] > id))) {
+          tk[p] = tk[p - 1];
+          ti[p] = ti[p - 1];
+          --p;
+        }
+        tk[p] = v;
+        ti[p] = id;
+      }
+    }
+    __syncthreads();
+    if (t < TILE) {
+      mn = topk[t * K + K - 1];
+      mp = K - 1;
+    }
   };
 
   scan_tiles(0, nshort, true);
@@ -810,11 +885,87 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
     hi = s + es;
   };
 
-  // Pass 1: every pair.  0 no, 1 yes, 2 long (flagged), 3 resolve.
-  for (int ci = 0; ci < nch; ++ci) {
-    const int32_t c = clist[ci];
-    if (t >= bv.cfill[c]) continue;
-    const int64_t slot = (int64_t)c * kPairChunk + t;
+  // Pass 1: every pair, four chunks at a time (independent loads).
+  // Classes: 0 no, 1 yes, 2 long (flagged), 3 resolve.
+  constexpr int PG = 4;
+  for (int cg = 0; cg < nch; cg += PG) {
+    int64_t slot[PG];
+    bool ok[PG];
+#pragma unroll
+    for (int g = 0; g < PG; ++g) {
+      ok[g] = false;
+      slot[g] = 0;
+      if (cg + g < nch) {
+        const int32_t c = clist[cg + g];
+        ok[g] = t < bv.cfill[c];
+        slot[g] = (int64_t)c * kPairChunk + t;
+      }
+    }
+    int64_t uu[PG];
+    int32_t jv[PG];
+    float sv[PG];
+#pragma unroll
+    for (int g = 0; g < PG; ++g) {
+      uu[g] = ok[g] ? bv.pair_u[slot[g]] : B * TILE;
+      jv[g] = ok[g] ? bv.pair_j[slot[g]] : 0;
+      sv[g] = ok[g] ? bv.pair_s[slot[g]] : 0.f;
+    }
+    int kv[PG];
+    float nqv[PG], nuv[PG];
+#pragma unroll
+    for (int g = 0; g < PG; ++g) {
+      kv[g] = ok[g] ? bv.k_s[jv[g]] : 1;
+      nqv[g] = ok[g] ? bv.qn_s[jv[g]] : 0.f;
+      nuv[g] = ok[g] ? ix.normQ[uu[g]] : 0.f;
+    }
+#pragma unroll
+    for (int g = 0; g < PG; ++g) {
+      if (!ok[g]) continue;
+      const int64_t u = uu[g];
+      const int ul = (int)(u - B * TILE);
+      const int32_t jj = jv[g];
+      const int k = kv[g];
+      const float nu = nuv[g];
+      const float e = e0 * nu + ix.eps_abs;
+      const float kth = topk[ul * K + k - 1];
+      int cls;
+      float lo = 0.f, hi = 0.f;
+      const float eb = ix.eps_rel * (nu * nqv[g]) + ix.eps_abs;  // bulk-precision bound
+      if (kth - e > sv[g] + eb) {
+        cls = 0;
+      } else {
+        pair_bounds(slot[g], ul, jj, nu, lo, hi);
+        const float csu = ix.cs_inflate * nu;
+        if (kth - e > hi) {
+          cls = 0;
+        } else if (lo >= csu * ix.normP[k - 1]) {
+          cls = 1;  // Lemma 2
+          ++c_l2;
+        } else if (S0 >= ix.m || csu * ix.normP[S0] <= lo) {
+          cls = (kth + e <= lo) ? 1 : 3;
+        } else {
+          cls = 2;
+          atomicMax(&Tu[ul], norm_limit(ix, csu, lo, (int)S0));
+        }
+      }
+      bv.pair_st[slot[g]] = cls == 2;
+      if (cls == 2) {
+        const int at = atomicAdd(&nflag, 1);
+        if (at < kFlagCap) flist[at] = (int32_t)slot[g];
+        ++c_long;
+      }
+      bool yes = cls == 1;
+      if (cls == 3) {
+        yes = resolve_pair(ix, bv, u, jj, k, lo, hi, nu, topk + ul * K, topi + ul * K, K, c_full);
+        ++c_f64;
+      }
+      if (yes) set_pair_result(bv, ix, u, bv.perm[jj]);
+    }
+  }
+  __syncthreads();
+
+  // Long pass: flagged pairs, their users' scan continued to each user's limit.
+  auto decide_flagged = [&](int64_t slot) {
     const int64_t u = bv.pair_u[slot];
     const int ul = (int)(u - B * TILE);
     const int32_t jj = bv.pair_j[slot];
@@ -822,67 +973,33 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
     const float nu = ix.normQ[u];
     const float e = e0 * nu + ix.eps_abs;
     const float kth = topk[ul * K + k - 1];
-    int cls;
-    float lo = 0.f, hi = 0.f;
-    const float sb = bv.pair_s[slot];
-    const float eb = ix.eps_rel * (nu * bv.qn_s[jj]) + ix.eps_abs;  // bulk-precision bound
-    if (kth - e > sb + eb) {
-      cls = 0;
+    float lo, hi;
+    pair_bounds(slot, ul, jj, nu, lo, hi);
+    bool yes;
+    if (kth - e > hi) {
+      yes = false;
+    } else if (kth + e <= lo) {
+      yes = true;
     } else {
-      pair_bounds(slot, ul, jj, nu, lo, hi);
-      const float csu = ix.cs_inflate * nu;
-      if (kth - e > hi) {
-        cls = 0;
-      } else if (lo >= csu * ix.normP[k - 1]) {
-        cls = 1;  // Lemma 2
-        ++c_l2;
-      } else if (S0 >= ix.m || csu * ix.normP[S0] <= lo) {
-        cls = (kth + e <= lo) ? 1 : 3;
-      } else {
-        cls = 2;
-        atomicMax(&Tu[ul], norm_limit(ix, csu, lo, (int)S0));
-      }
-    }
-    bv.pair_st[slot] = cls == 2;
-    if (cls == 2) atomicAdd(&nflag, 1);
-    bool yes = cls == 1;
-    if (cls == 3) {
-      yes = resolve_pair(ix, bv, u, jj, k, lo, hi, nu, topk + ul * K, topi + ul * K, K);
+      yes = resolve_pair(ix, bv, u, jj, k, lo, hi, nu, topk + ul * K, topi + ul * K, K, c_full);
       ++c_f64;
     }
     if (yes) set_pair_result(bv, ix, u, bv.perm[jj]);
-  }
-  __syncthreads();
-
-  // Long pass: flagged pairs, their users' scan continued to each user's limit.
-  if (nflag > 0) {
+  };
+  const int nfl = nflag;
+  if (nfl > 0) {
     int tmax = 0;
     for (int i = 0; i < TILE; ++i) tmax = max(tmax, Tu[i]);
     scan_tiles(nshort, (int)((tmax + TILE - 1) / TILE), false);
-    for (int ci = 0; ci < nch; ++ci) {
-      const int32_t c = clist[ci];
-      if (t >= bv.cfill[c]) continue;
-      const int64_t slot = (int64_t)c * kPairChunk + t;
-      if (!bv.pair_st[slot]) continue;
-      const int64_t u = bv.pair_u[slot];
-      const int ul = (int)(u - B * TILE);
-      const int32_t jj = bv.pair_j[slot];
-      const int k = bv.k_s[jj];
-      const float nu = ix.normQ[u];
-      const float e = e0 * nu + ix.eps_abs;
-      const float kth = topk[ul * K + k - 1];
-      float lo, hi;
-      pair_bounds(slot, ul, jj, nu, lo, hi);
-      bool yes;
-      if (kth - e > hi) {
-        yes = false;
-      } else if (kth + e <= lo) {
-        yes = true;
-      } else {
-        yes = resolve_pair(ix, bv, u, jj, k, lo, hi, nu, topk + ul * K, topi + ul * K, K);
-        ++c_f64;
+    if (nfl <= kFlagCap) {
+      for (int i = t; i < nfl; i += 256) decide_flagged(flist[i]);
+    } else {  // more than the list holds: find them by their flags
+      for (int ci = 0; ci < nch; ++ci) {
+        const int32_t c = clist[ci];
+        if (t >= bv.cfill[c]) continue;
+        const int64_t slot = (int64_t)c * kPairChunk + t;
+        if (bv.pair_st[slot]) decide_flagged(slot);
       }
-      if (yes) set_pair_result(bv, ix, u, bv.perm[jj]);
     }
   }
 
@@ -891,8 +1008,12 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
       c_l2 += __shfl_xor(c_l2, off);
       c_f64 += __shfl_xor(c_f64, off);
       c_scan += __shfl_xor(c_scan, off);
+      c_long += __shfl_xor(c_long, off);
+      c_full += __shfl_xor(c_full, off);
     }
     if (lane == 0) {
+      if (c_long) atomicAdd(&bv.ctr[C_LONG], c_long);
+      if (c_full) atomicAdd(&bv.ctr[C_F64SCAN], c_full);
       if (c_l2) atomicAdd(&bv.ctr[C_L2YES], c_l2);
       if (c_f64) atomicAdd(&bv.ctr[C_RCHK], c_f64);
       if (c_scan) atomicAdd(&bv.ctr[C_SCAN], c_scan);
@@ -1035,7 +1156,8 @@ void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
 
 size_t bscan_lds_bytes(const DevIndex& ix) {
   const size_t d2 = (size_t)(ix.d + (ix.d & 1));
-  return (2 * d2 * TILE + TILE * (TILE + 1) + 2 * (size_t)TILE * (ix.kmax + 2) + TILE) * 4;
+  return (2 * d2 * TILE + TILE * TILE + 2 * (size_t)TILE * bscan_list_len(ix.kmax) + 3 * TILE) * 4 +
+         TILE * TILE;
 }
 
 template <int NV>

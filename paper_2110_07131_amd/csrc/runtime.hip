@@ -478,7 +478,11 @@ rk_status check_batch_ks(rk_index* h, const int32_t* ks, int64_t nq) {
 }
 
 constexpr int64_t kBitmapBudget = 512ll << 20;  // bytes of per-query result bits per chunk
-constexpr int64_t kPairBudget = 1ll << 26;       // undecided-pair list entries per chunk
+// Undecided-pair slots per chunk of queries.  Exact table: only the pairs
+// within rounding of theta_k (rechecks); bounded table: every survivor of the
+// filter goes to the scan.
+constexpr int64_t kPairBudgetExact = 1ll << 24;
+constexpr int64_t kPairBudget = 1ll << 27;
 constexpr size_t kMaxLds = 160 * 1024;
 
 rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
@@ -494,8 +498,19 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
   b.pair_st = b.cfill = b.nchunks = b.bcnt = b.bchunks = nullptr;
   const DevIndex& ix = h->ix;
   const int64_t cp = round_up(chunk, TILE), W = (ix.n + 31) / 32;
-  int64_t pc = std::min<int64_t>((int64_t)chunk * std::max<int64_t>(ix.n_pad, 1), kPairBudget);
+  int64_t pc = std::min<int64_t>((int64_t)chunk * std::max<int64_t>(ix.n_pad, 1),
+                                 ix.exact ? kPairBudgetExact : kPairBudget);
   if (h->opts.pair_cap > 0) pc = h->opts.pair_cap;
+  int64_t chunk_cap = 0;
+  if (!ix.exact) {
+    // Chunks of kPairChunk slots: every chunk is full but the one each of a
+    // block's four filter waves is filling, so pc pairs need at most
+    // pc / kPairChunk + 4 nB chunks (an explicit pair_cap is taken as is).
+    chunk_cap = h->opts.pair_cap > 0 ? pc / kPairChunk
+                                     : (pc + kPairChunk - 1) / kPairChunk + 4 * (int64_t)ix.nB;
+    chunk_cap = std::min<int64_t>(chunk_cap, INT32_MAX / kPairChunk);
+    pc = std::max<int64_t>(pc, chunk_cap * kPairChunk);
+  }
   b.qcap = 0;
   HIPTRY(h->dalloc(&b.qn, chunk));
   HIPTRY(h->dalloc(&b.perm, chunk));
@@ -514,7 +529,7 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
   if (!ix.exact) {
     // Chunks of kPairChunk slots; a block's chunks are all full but the one
     // each of its four filter waves is filling: at most 64 * cp / kPairChunk + 4.
-    b.chunk_cap = (int32_t)std::min<int64_t>(pc / kPairChunk, INT32_MAX);
+    b.chunk_cap = (int32_t)chunk_cap;
     b.maxc = (int32_t)(TILE * cp / kPairChunk + 4);
     HIPTRY(h->dalloc(&b.pair_st, std::max<int64_t>(pc, 1)));
     HIPTRY(h->dalloc(&b.cfill, std::max<int64_t>(b.chunk_cap, 1)));
@@ -561,7 +576,7 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
   if (nq == 0) return RK_OK;
   const size_t tile_bytes = ix.bf16 ? (size_t)ix.d16 * TILE * 2 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
   if (bfilter_lds_bytes(ix) > kMaxLds || tile_bytes > bfilter_max_tile_bytes() ||
-      (!ix.exact && bscan_lds_bytes(ix) > kMaxLds)) {
+      (!ix.exact && bscan_lds_bytes(ix) + 8192 > kMaxLds)) {  // + static LDS of the scan
     // too wide for the block-resident batched filter: one query at a time
     for (int64_t i = 0; i < nq; ++i) {
       rk_status st = enqueue_query(h, qs_dev + i * ix.d, ks[i], ids, cap, offs + i, offs + i + 1,
@@ -820,6 +835,7 @@ rk_status rk_index_stats(const rk_index* hc, rk_stats* o) {
   o->blocks_visited = c[C_BLOCKS]; o->blocks_pruned = c[C_PRUNED]; o->users_evaluated = c[C_USERS];
   o->lemma1_no = c[C_L1NO]; o->lemma2_yes = c[C_L2YES]; o->table_yes = c[C_TYES];
   o->survivors = c[C_SURV]; o->scan_items = c[C_SCAN]; o->rechecks = c[C_RCHK]; o->results = c[C_RES];
+  o->scan_long = c[C_LONG]; o->scan_full_f64 = c[C_F64SCAN];
   return RK_OK;
 }
 

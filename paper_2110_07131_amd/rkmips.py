@@ -59,7 +59,8 @@ class Stats(ctypes.Structure):
                 ("lemma2_yes", ctypes.c_int64), ("table_yes", ctypes.c_int64),
                 ("survivors", ctypes.c_int64), ("scan_items", ctypes.c_int64),
                 ("rechecks", ctypes.c_int64), ("results", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 8)]
+                ("scan_long", ctypes.c_int64), ("scan_full_f64", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 6)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -167,3 +167,25 @@ def test_grouped_scan_short_catalog(m):
     off, ids = idx.reverse_kmips_batch(qs, ks)
     check_csr(w.Q, w.P, qs, ks, off, ids)
     idx.free()
+
+
+@pytest.mark.parametrize("nq", [10, 30])
+def test_grouped_scan_many_flagged_pairs(nq):
+    # Users along +x; 600 large items along -x (they never beat q, but their
+    # norms put every pair's Corollary 1 limit past the short pass) and 20
+    # small random items: every pair is flagged for the long pass, more than
+    # the workgroup's list of flagged pairs holds when nq = 30 (64 x 30).
+    rng = np.random.default_rng(40 + nq)
+    Q = np.column_stack([1 + 0.1 * rng.random(64), 0.2 * rng.standard_normal(64)]).astype(np.float32)
+    big = np.column_stack([-3 - rng.random(600), 0.3 * rng.standard_normal(600)])
+    small = 0.6 * rng.standard_normal((20, 2))
+    P = np.vstack([big, small]).astype(np.float32)
+    qs = np.column_stack([0.4 + 0.2 * rng.random(nq), 0.1 * rng.standard_normal(nq)]).astype(np.float32)
+    ks = rng.integers(1, 6, nq).astype(np.int32)
+    idx = Index.build(Q, P, 5, lb_items=8)
+    idx.set_counting(True)
+    off, ids = idx.reverse_kmips_batch(qs, ks)
+    check_csr(Q, P, qs, ks, off, ids)
+    st = idx.stats()
+    assert st["scan_long"] >= 64 * nq * 0.9
+    idx.free()
