@@ -44,7 +44,7 @@ def parse():
 
 
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
-KERNEL_NAMES = {"filter": "k_filter", "batch_filter": "k_bfilter", "batch_pairs": "k_brecheck_exact/k_bverify",
+KERNEL_NAMES = {"filter": "k_filter", "batch_filter": "k_bfilter", "batch_pairs": "k_brecheck_exact/k_bscan",
                 "batch_assemble": "k_bscan+k_bassemble", "batch_prep": "k_bnorms+k_bsort+k_btile",
                 "recheck": "k_recheck", "finalize": "k_finalize", "verify": "k_verify"}
 
@@ -59,6 +59,16 @@ def dominant_roofline(cls: str, times, st: dict, d: int, precision: str) -> dict
     norm + bound) per evaluated block."""
     ms, launches = times
     avg_s = ms / 1e3 / max(launches, 1)
+    if cls == "batch_pairs" and st["scan_items"] > 0:
+        # bounded table: the grouped scan's float32 MFMA products, 2*d flops
+        # per (user, item) product of the scanned prefixes
+        flops = 2.0 * d * st["scan_items"] / max(launches, 1)
+        ach = flops / avg_s / 1e12
+        peak = MFMA_PEAK_TFLOPS["fp32"]
+        return {"bound": "mfma", "kernel": "k_bscan", "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "avg_launch_us": avg_s * 1e6,
+                "launches_per_step": launches, "algorithmic_flops_per_launch": flops,
+                "traffic": None}
     if cls == "batch_filter":
         flops = 2.0 * d * st["users_evaluated"] / max(launches, 1)
         ach = flops / avg_s / 1e12
