@@ -224,6 +224,78 @@ void rk_index_free(rk_index *idx);
 /* Message of the last error on the calling thread ("" if none). */
 const char *rk_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Serving: the online phase (Algorithm 3; Theorem 2 bounds its cost per
+ * query) under a stream of single-query requests over several resident
+ * catalogs.  A server owns one worker thread that batches the pending
+ * requests of a catalog continuously (whatever is queued when the device
+ * becomes free, up to max_batch) and runs them through the batched path of
+ * that catalog's index; results come back to the host per request.
+ *
+ * Catalogs are admitted by device-memory footprint: the index's own bytes
+ * plus the batch workspace and the server's buffers for max_batch queries
+ * must fit in what is left of hbm_budget, else RK_E_NOMEM.
+ *
+ * A catalog's index is borrowed: it must outlive the server, and nothing
+ * else may query it while the server runs.  Requests for different catalogs
+ * never share a launch, so a catalog's results do not depend on the others'
+ * traffic.  All functions are thread-safe.
+ * ---------------------------------------------------------------------- */
+typedef struct rk_server rk_server;
+
+typedef struct {
+    int32_t device;       /* HIP device of the catalogs */
+    int32_t max_batch;    /* 0 -> 1024: queries per launch (per catalog) */
+    int32_t max_wait_us;  /* 0: launch as soon as the device is free;
+                             > 0: a batch smaller than max_batch may wait up
+                             to this long after its oldest request arrived */
+    int32_t reserved0;
+    int64_t hbm_budget;   /* 0 -> 90% of the device memory free at creation */
+    int64_t reserved[6];
+} rk_server_opts;
+
+typedef struct {
+    int64_t tag;          /* the caller's tag from rk_server_submit */
+    int32_t catalog;
+    int32_t status;       /* rk_status of the query */
+    int64_t count;        /* result size (ascending original user ids) */
+    int64_t ids_offset;   /* first id in the buffer passed to rk_server_poll */
+    double submit_ms;     /* server clock, ms since rk_server_create */
+    double done_ms;       /* result on the host */
+} rk_completion;
+
+void rk_server_opts_default(rk_server_opts *o);
+rk_status rk_server_create(const rk_server_opts *opts, rk_server **out);
+
+/* Admit a built index as a catalog; *catalog receives its number (0, 1, ...).
+ * The index's batch workspace for max_batch queries is allocated here. */
+rk_status rk_server_add_catalog(rk_server *s, rk_index *idx, int32_t *catalog);
+
+/* Queue one query (host vector of the catalog's d floats, copied) at k.
+ * RK_E_INVAL: bad catalog, k < 1 or a non-finite value; RK_E_KMAX: k >
+ * k_max (no rebuild while serving). */
+rk_status rk_server_submit(rk_server *s, int32_t catalog, const float *q, int32_t k,
+                           int64_t tag);
+
+/* Move up to max_out finished requests out of the server, oldest first:
+ * their records to out[], their ids one after another into ids[0..ids_cap).
+ * Waits up to wait_us microseconds for a first one when none is finished.
+ * Returns the number of records written (0 if none finished), or -1 when
+ * the next finished request alone has more ids than ids_cap (it stays in
+ * the server; the message gives its size). */
+int64_t rk_server_poll(rk_server *s, rk_completion *out, int64_t max_out, int32_t *ids,
+                       int64_t ids_cap, int32_t wait_us);
+
+/* Requests submitted and not yet finished by the worker. */
+int64_t rk_server_inflight(rk_server *s);
+
+/* Device bytes held by the admitted catalogs (indices, workspaces, buffers). */
+int64_t rk_server_used_bytes(rk_server *s);
+
+/* Finish the queued requests, stop the worker, release the server's own
+ * buffers (not the indices).  Unpolled results are dropped. */
+void rk_server_free(rk_server *s);
+
 #ifdef __cplusplus
 }
 #endif

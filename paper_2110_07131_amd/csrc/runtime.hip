@@ -4,10 +4,14 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rk_batch.h"
@@ -485,6 +489,49 @@ constexpr int64_t kPairBudgetExact = 1ll << 24;
 constexpr int64_t kPairBudget = 1ll << 27;
 constexpr size_t kMaxLds = 160 * 1024;
 
+// Sizes of the batched path's workspace for chunks of `chunk` queries.
+struct BatchSizes {
+  int64_t pc = 0;         // pair slots
+  int64_t chunk_cap = 0;  // pair chunks (bounded table)
+  int64_t maxc = 0;       // chunk-list capacity per block (bounded table)
+  int64_t bytes = 0;      // device bytes of the whole workspace
+};
+
+BatchSizes batch_sizes(const rk_index* h, int32_t chunk) {
+  const DevIndex& ix = h->ix;
+  BatchSizes z;
+  const int64_t cp = round_up(chunk, TILE), W = std::max<int64_t>((ix.n + 31) / 32, 1);
+  int64_t pc = std::min<int64_t>((int64_t)chunk * std::max<int64_t>(ix.n_pad, 1),
+                                 ix.exact ? kPairBudgetExact : kPairBudget);
+  if (h->opts.pair_cap > 0) pc = h->opts.pair_cap;
+  if (!ix.exact) {
+    // Chunks of kPairChunk slots: every chunk is full but the one each of a
+    // block's four filter waves is filling, so pc pairs need at most
+    // pc / kPairChunk + 4 nB chunks (an explicit pair_cap is taken as is).
+    z.chunk_cap = h->opts.pair_cap > 0 ? pc / kPairChunk
+                                       : (pc + kPairChunk - 1) / kPairChunk + 4 * (int64_t)ix.nB;
+    z.chunk_cap = std::min<int64_t>(z.chunk_cap, INT32_MAX / kPairChunk);
+    pc = std::max<int64_t>(pc, z.chunk_cap * kPairChunk);
+    z.maxc = TILE * cp / kPairChunk + 4;
+  }
+  z.pc = pc;
+  const int64_t d2 = ix.d + (ix.d & 1);
+  int64_t b = chunk * 4 * 2 + cp * d2 * 4 + (ix.bf16 ? cp * ix.d16 * 2 : 0) + cp * 8 +
+              chunk * W * 4 + chunk * 8 + chunk + 4 + pc * 12 + chunk * 4;
+  if (!ix.exact)
+    b += std::max<int64_t>(pc, 1) * 4 + std::max<int64_t>(z.chunk_cap, 1) * 4 + 4 +
+         std::max<int64_t>(ix.nB, 1) * 4 * (1 + z.maxc);
+  z.bytes = b;
+  return z;
+}
+
+// Queries per chunk of the batched path for a batch of nq queries.
+int32_t batch_chunk(const rk_index* h, int64_t nq) {
+  const int64_t W = std::max<int64_t>((h->ix.n + 31) / 32, 1);
+  return (int32_t)std::max<int64_t>(
+      1, std::min<int64_t>({nq, (int64_t)kBatchChunkMax, kBitmapBudget / (W * 4)}));
+}
+
 rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
   auto& b = h->bw;
   if (b.qcap >= chunk) return RK_OK;
@@ -497,20 +544,9 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
     if (p) h->dfree(p);
   b.pair_st = b.cfill = b.nchunks = b.bcnt = b.bchunks = nullptr;
   const DevIndex& ix = h->ix;
+  const BatchSizes z = batch_sizes(h, chunk);
   const int64_t cp = round_up(chunk, TILE), W = (ix.n + 31) / 32;
-  int64_t pc = std::min<int64_t>((int64_t)chunk * std::max<int64_t>(ix.n_pad, 1),
-                                 ix.exact ? kPairBudgetExact : kPairBudget);
-  if (h->opts.pair_cap > 0) pc = h->opts.pair_cap;
-  int64_t chunk_cap = 0;
-  if (!ix.exact) {
-    // Chunks of kPairChunk slots: every chunk is full but the one each of a
-    // block's four filter waves is filling, so pc pairs need at most
-    // pc / kPairChunk + 4 nB chunks (an explicit pair_cap is taken as is).
-    chunk_cap = h->opts.pair_cap > 0 ? pc / kPairChunk
-                                     : (pc + kPairChunk - 1) / kPairChunk + 4 * (int64_t)ix.nB;
-    chunk_cap = std::min<int64_t>(chunk_cap, INT32_MAX / kPairChunk);
-    pc = std::max<int64_t>(pc, chunk_cap * kPairChunk);
-  }
+  const int64_t pc = z.pc;
   b.qcap = 0;
   HIPTRY(h->dalloc(&b.qn, chunk));
   HIPTRY(h->dalloc(&b.perm, chunk));
@@ -527,10 +563,8 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
   HIPTRY(h->dalloc(&b.pair_s, pc));
   HIPTRY(h->dalloc(&b.ks_dev, chunk));
   if (!ix.exact) {
-    // Chunks of kPairChunk slots; a block's chunks are all full but the one
-    // each of its four filter waves is filling: at most 64 * cp / kPairChunk + 4.
-    b.chunk_cap = (int32_t)chunk_cap;
-    b.maxc = (int32_t)(TILE * cp / kPairChunk + 4);
+    b.chunk_cap = (int32_t)z.chunk_cap;
+    b.maxc = (int32_t)z.maxc;
     HIPTRY(h->dalloc(&b.pair_st, std::max<int64_t>(pc, 1)));
     HIPTRY(h->dalloc(&b.cfill, std::max<int64_t>(b.chunk_cap, 1)));
     HIPTRY(h->dalloc(&b.nchunks, 1));
@@ -586,8 +620,7 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
     return RK_OK;
   }
   const int64_t W = std::max<int64_t>((ix.n + 31) / 32, 1);
-  const int32_t chunk = (int32_t)std::max<int64_t>(
-      1, std::min<int64_t>({nq, (int64_t)kBatchChunkMax, kBitmapBudget / (W * 4)}));
+  const int32_t chunk = batch_chunk(h, nq);
   rk_status st = ensure_batch_ws(h, chunk);
   if (st != RK_OK) return st;
   auto& b = h->bw;
@@ -615,6 +648,200 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
 }
 
 }  // namespace
+
+// ===========================================================================
+// Serving: continuous batching over resident catalogs (rk_server_*).
+namespace {
+
+struct ServerReq {
+  int32_t k = 0;
+  int64_t tag = 0;
+  double t_submit = 0;
+  std::vector<float> q;
+};
+
+struct ServerDone {
+  rk_completion c{};
+  std::vector<int32_t> ids;
+};
+
+struct ServerCatalog {
+  rk_index* idx = nullptr;
+  int32_t d = 0;
+  std::deque<ServerReq> queue;
+  hipStream_t stream = nullptr;
+  float* q_dev = nullptr;
+  int64_t* offs_dev = nullptr;
+  int32_t* ids_dev = nullptr;
+  int64_t ids_cap = 0;
+  float* q_pin = nullptr;
+  int64_t* offs_pin = nullptr;
+  int32_t* ids_pin = nullptr;
+  int64_t bytes = 0;  // device bytes charged to the budget
+};
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void free_catalog_buffers(ServerCatalog* c) {
+  if (c->q_dev) (void)hipFree(c->q_dev);
+  if (c->offs_dev) (void)hipFree(c->offs_dev);
+  if (c->ids_dev) (void)hipFree(c->ids_dev);
+  if (c->q_pin) (void)hipHostFree(c->q_pin);
+  if (c->offs_pin) (void)hipHostFree(c->offs_pin);
+  if (c->ids_pin) (void)hipHostFree(c->ids_pin);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  c->q_dev = nullptr;
+  c->offs_dev = nullptr;
+  c->ids_dev = nullptr;
+  c->q_pin = nullptr;
+  c->offs_pin = nullptr;
+  c->ids_pin = nullptr;
+  c->stream = nullptr;
+}
+
+hipError_t alloc_ids(ServerCatalog* c, int64_t cap) {
+  if (c->ids_dev) (void)hipFree(c->ids_dev);
+  if (c->ids_pin) (void)hipHostFree(c->ids_pin);
+  c->ids_dev = nullptr;
+  c->ids_pin = nullptr;
+  c->ids_cap = 0;
+  hipError_t e = hipMalloc((void**)&c->ids_dev, cap * sizeof(int32_t));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->ids_pin, cap * sizeof(int32_t), hipHostMallocDefault);
+  if (e == hipSuccess) c->ids_cap = cap;
+  return e;
+}
+
+}  // namespace
+
+struct rk_server {
+  rk_server_opts opts{};
+  std::chrono::steady_clock::time_point t0;
+  std::vector<ServerCatalog*> cats;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<ServerDone> done;
+  int64_t inflight = 0;
+  int64_t used = 0;
+  int64_t budget = 0;
+  bool stop = false;
+  std::thread worker;
+
+  bool pending() const {
+    for (const ServerCatalog* c : cats)
+      if (!c->queue.empty()) return true;
+    return false;
+  }
+
+  // One launch for the queued requests of catalog c, results to the host.
+  void run_batch(int32_t ci, ServerCatalog* c, std::vector<ServerReq>& batch) {
+    const int64_t nq = (int64_t)batch.size();
+    const int d = c->d;
+    std::vector<int32_t> ks(nq);
+    for (int64_t i = 0; i < nq; ++i) {
+      std::memcpy(c->q_pin + i * d, batch[i].q.data(), d * sizeof(float));
+      ks[i] = batch[i].k;
+    }
+    rk_status st = RK_OK;
+    int64_t total = 0;
+    hipError_t e = hipMemcpyAsync(c->q_dev, c->q_pin, nq * d * sizeof(float), hipMemcpyHostToDevice, c->stream);
+    for (int attempt = 0; attempt < 2 && e == hipSuccess; ++attempt) {
+      st = batch_enqueue(c->idx, c->q_dev, nq, ks.data(), c->offs_dev, c->ids_dev, c->ids_cap, c->stream);
+      if (st != RK_OK) break;
+      e = hipMemcpyAsync(c->offs_pin, c->offs_dev, (nq + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) break;
+      total = c->offs_pin[nq];
+      if (total <= c->ids_cap) break;
+      // more results than the id buffers hold: grow them, run the batch again
+      const int64_t old = c->ids_cap;
+      e = alloc_ids(c, total + total / 4 + 1024);
+      std::lock_guard<std::mutex> lk(mu);
+      used += (c->ids_cap - old) * (int64_t)sizeof(int32_t);
+      c->bytes += (c->ids_cap - old) * (int64_t)sizeof(int32_t);
+    }
+    if (e == hipSuccess && st == RK_OK && total > 0) {
+      e = hipMemcpyAsync(c->ids_pin, c->ids_dev, total * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (st == RK_OK && e != hipSuccess) st = e == hipErrorOutOfMemory ? RK_E_NOMEM : RK_E_DEVICE;
+    const double t_done = ms_since(t0);
+    std::lock_guard<std::mutex> lk(mu);
+    for (int64_t i = 0; i < nq; ++i) {
+      ServerDone dn;
+      dn.c.tag = batch[i].tag;
+      dn.c.catalog = ci;
+      dn.c.status = st;
+      dn.c.submit_ms = batch[i].t_submit;
+      dn.c.done_ms = t_done;
+      if (st == RK_OK) {
+        const int64_t a = c->offs_pin[i], b = c->offs_pin[i + 1];
+        dn.c.count = b - a;
+        dn.ids.assign(c->ids_pin + a, c->ids_pin + b);
+      }
+      done.push_back(std::move(dn));
+    }
+    inflight -= nq;
+    cv_done.notify_all();
+  }
+
+  void loop() {
+    (void)hipSetDevice(opts.device);
+    size_t rr = 0;
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      cv_work.wait(lk, [&] { return stop || pending(); });
+      if (!pending()) {
+        if (stop) break;
+        continue;
+      }
+      int32_t ci = 0;
+      for (size_t j = 0; j < cats.size(); ++j) {
+        const size_t c = (rr + j) % cats.size();
+        if (!cats[c]->queue.empty()) {
+          ci = (int32_t)c;
+          break;
+        }
+      }
+      rr = (size_t)ci + 1;
+      ServerCatalog* c = cats[ci];
+      if (opts.max_wait_us > 0) {
+        const double deadline = c->queue.front().t_submit + opts.max_wait_us / 1000.0;
+        while (!stop && (int64_t)c->queue.size() < opts.max_batch) {
+          const double left = deadline - ms_since(t0);
+          if (left <= 0) break;
+          cv_work.wait_for(lk, std::chrono::duration<double, std::milli>(left));
+        }
+      }
+      const int64_t nb = std::min<int64_t>((int64_t)c->queue.size(), opts.max_batch);
+      std::vector<ServerReq> batch;
+      batch.reserve(nb);
+      for (int64_t i = 0; i < nb; ++i) {
+        batch.push_back(std::move(c->queue.front()));
+        c->queue.pop_front();
+      }
+      lk.unlock();
+      run_batch(ci, c, batch);
+      lk.lock();
+    }
+  }
+
+  ~rk_server() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv_work.notify_all();
+    if (worker.joinable()) worker.join();
+    (void)hipSetDevice(opts.device);
+    for (ServerCatalog* c : cats) {
+      if (c->stream) (void)hipStreamSynchronize(c->stream);
+      free_catalog_buffers(c);
+      delete c;
+    }
+  }
+};
 
 // ===========================================================================
 extern "C" {
@@ -886,5 +1113,157 @@ int64_t rk_index_footprint(int64_t n, int64_t m, int32_t d, int32_t k_max, const
   b += ((n + 31) / 32) * 4 + np * 12 + 4 * 4 + 4 + 16 * 8 + d * 4 + std::max<int64_t>(n, 1) * 4 + 8;
   return b;
 }
+
+void rk_server_opts_default(rk_server_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->max_batch = 1024;
+}
+
+rk_status rk_server_create(const rk_server_opts* opts, rk_server** out) {
+  if (!out) return fail(RK_E_INVAL, "out is NULL");
+  *out = nullptr;
+  rk_server_opts o;
+  rk_server_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.max_batch == 0) o.max_batch = 1024;
+  if (o.max_batch < 0 || o.max_wait_us < 0 || o.hbm_budget < 0)
+    return fail(RK_E_INVAL, "max_batch, max_wait_us and hbm_budget must be >= 0");
+  int ndev = 0;
+  HIPTRY(hipGetDeviceCount(&ndev));
+  if (o.device < 0 || o.device >= ndev) return fail(RK_E_INVAL, "no such device");
+  HIPTRY(hipSetDevice(o.device));
+  int64_t budget = o.hbm_budget;
+  if (budget == 0) {
+    size_t fr = 0, tot = 0;
+    HIPTRY(hipMemGetInfo(&fr, &tot));
+    budget = (int64_t)(0.9 * (double)fr);
+  }
+  rk_server* s = new rk_server();
+  s->opts = o;
+  s->budget = budget;
+  s->t0 = std::chrono::steady_clock::now();
+  s->worker = std::thread([s] { s->loop(); });
+  *out = s;
+  return RK_OK;
+}
+
+rk_status rk_server_add_catalog(rk_server* s, rk_index* h, int32_t* catalog) {
+  if (!s || !h || !catalog) return fail(RK_E_INVAL, "NULL argument");
+  if (h->device != s->opts.device) return fail(RK_E_INVAL, "the index is on another device");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (const ServerCatalog* c : s->cats)
+      if (c->idx == h) return fail(RK_E_INVAL, "the index is already a catalog of this server");
+  }
+  HIPTRY(hipSetDevice(s->opts.device));
+  const int64_t B = s->opts.max_batch, d = h->ix.d;
+  const int32_t chunk = batch_chunk(h, B);
+  const int64_t ws = h->bw.qcap >= chunk ? 0 : batch_sizes(h, chunk).bytes;
+  const int64_t ids0 = B * 64;
+  const int64_t bufs = B * d * 4 + (B + 1) * 8 + ids0 * 4;
+  const int64_t need = (int64_t)h->footprint + ws + bufs;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->used + need > s->budget)
+      return fail(RK_E_NOMEM, "admission: the catalog needs " + std::to_string(need) + " device bytes, " +
+                                  std::to_string(s->budget - s->used) + " of the budget are left");
+    s->used += need;
+  }
+  auto c = new ServerCatalog();
+  c->idx = h;
+  c->d = (int32_t)d;
+  c->bytes = need;
+  auto undo = [&](rk_status st) {
+    free_catalog_buffers(c);
+    delete c;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->used -= need;
+    return st;
+  };
+  rk_status st = ensure_batch_ws(h, chunk);
+  if (st != RK_OK) return undo(st);
+  hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->q_dev, std::max<int64_t>(B * d, 1) * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->offs_dev, (B + 1) * sizeof(int64_t));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->q_pin, std::max<int64_t>(B * d, 1) * sizeof(float), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->offs_pin, (B + 1) * sizeof(int64_t), hipHostMallocDefault);
+  if (e == hipSuccess) e = alloc_ids(c, ids0);
+  if (e != hipSuccess)
+    return undo(fail(e == hipErrorOutOfMemory ? RK_E_NOMEM : RK_E_DEVICE, hipGetErrorString(e)));
+  std::lock_guard<std::mutex> lk(s->mu);
+  *catalog = (int32_t)s->cats.size();
+  s->cats.push_back(c);
+  return RK_OK;
+}
+
+rk_status rk_server_submit(rk_server* s, int32_t catalog, const float* q, int32_t k, int64_t tag) {
+  if (!s || !q) return fail(RK_E_INVAL, "NULL argument");
+  ServerReq r;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (catalog < 0 || catalog >= (int32_t)s->cats.size()) return fail(RK_E_INVAL, "no such catalog");
+    const rk_index* h = s->cats[catalog]->idx;
+    if (k < 1) return fail(RK_E_INVAL, "k must be >= 1");
+    if (k > h->ix.kmax) return fail(RK_E_KMAX, "k > k_max of the catalog");
+    r.q.assign(q, q + h->ix.d);
+  }
+  if (!host_values_ok(r.q.data(), (int64_t)r.q.size()))
+    return fail(RK_E_INVAL, "the query has a non-finite value or |x| >= 2^40");
+  r.k = k;
+  r.tag = tag;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    r.t_submit = ms_since(s->t0);
+    s->cats[catalog]->queue.push_back(std::move(r));
+    ++s->inflight;
+  }
+  s->cv_work.notify_one();
+  return RK_OK;
+}
+
+int64_t rk_server_poll(rk_server* s, rk_completion* out, int64_t max_out, int32_t* ids,
+                       int64_t ids_cap, int32_t wait_us) {
+  if (!s || max_out < 0 || ids_cap < 0 || (max_out > 0 && !out) || (ids_cap > 0 && !ids)) {
+    fail(RK_E_INVAL, "NULL argument or negative size");
+    return -1;
+  }
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->done.empty() && wait_us > 0)
+    s->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), [&] { return !s->done.empty(); });
+  int64_t n = 0, used = 0;
+  while (n < max_out && !s->done.empty()) {
+    ServerDone& dn = s->done.front();
+    const int64_t sz = (int64_t)dn.ids.size();
+    if (used + sz > ids_cap) {
+      if (n == 0) {
+        fail(RK_E_TRUNC, "the next finished request has " + std::to_string(sz) + " ids");
+        return -1;
+      }
+      break;
+    }
+    if (sz) std::memcpy(ids + used, dn.ids.data(), sz * sizeof(int32_t));
+    out[n] = dn.c;
+    out[n].ids_offset = used;
+    used += sz;
+    s->done.pop_front();
+    ++n;
+  }
+  return n;
+}
+
+int64_t rk_server_inflight(rk_server* s) {
+  if (!s) return -1;
+  std::lock_guard<std::mutex> lk(s->mu);
+  return s->inflight;
+}
+
+int64_t rk_server_used_bytes(rk_server* s) {
+  if (!s) return -1;
+  std::lock_guard<std::mutex> lk(s->mu);
+  return s->used;
+}
+
+void rk_server_free(rk_server* s) { delete s; }
 
 }  // extern "C"

@@ -29,6 +29,8 @@ EXPORTS = [
     "rk_index_set_counting", "rk_index_stats",
     "rk_index_reset_counters", "rk_index_export", "rk_index_rebuild", "rk_index_footprint",
     "rk_index_free", "rk_last_error",
+    "rk_server_opts_default", "rk_server_create", "rk_server_add_catalog", "rk_server_submit",
+    "rk_server_poll", "rk_server_inflight", "rk_server_used_bytes", "rk_server_free",
 ]
 
 
@@ -64,6 +66,18 @@ class Stats(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("max_wait_us", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64), ("reserved", ctypes.c_int64 * 6)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("catalog", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("count", ctypes.c_int64), ("ids_offset", ctypes.c_int64),
+                ("submit_ms", ctypes.c_double), ("done_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -124,6 +138,22 @@ def lib():
     L.rk_index_free.restype = None
     L.rk_last_error.argtypes = []
     L.rk_last_error.restype = ctypes.c_char_p
+    L.rk_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
+    L.rk_server_opts_default.restype = None
+    L.rk_server_create.argtypes = [ctypes.POINTER(ServerOpts), pidx]
+    L.rk_server_create.restype = ctypes.c_int
+    L.rk_server_add_catalog.argtypes = [vp, vp, ctypes.POINTER(i32)]
+    L.rk_server_add_catalog.restype = ctypes.c_int
+    L.rk_server_submit.argtypes = [vp, i32, vp, i32, i64]
+    L.rk_server_submit.restype = ctypes.c_int
+    L.rk_server_poll.argtypes = [vp, ctypes.POINTER(Completion), i64, vp, i64, i32]
+    L.rk_server_poll.restype = i64
+    L.rk_server_inflight.argtypes = [vp]
+    L.rk_server_inflight.restype = i64
+    L.rk_server_used_bytes.argtypes = [vp]
+    L.rk_server_used_bytes.restype = i64
+    L.rk_server_free.argtypes = [vp]
+    L.rk_server_free.restype = None
     _lib = L
     return L
 
@@ -292,3 +322,70 @@ class Index:
         _check(lib().rk_index_export(self._h, int(field), _ptr(out) or ctypes.c_void_p(1),
                                      out.nbytes))
         return out
+
+
+class Server:
+    """Continuous-batching server over resident catalogs (rk_server_*).
+
+    The indices added as catalogs are borrowed: keep them alive and do not
+    query them directly while the server runs (this object holds references).
+    """
+
+    def __init__(self, max_batch: int = 1024, max_wait_us: int = 0, hbm_budget: int = 0,
+                 device: int = 0):
+        o = ServerOpts()
+        lib().rk_server_opts_default(ctypes.byref(o))
+        o.device, o.max_batch, o.max_wait_us, o.hbm_budget = device, max_batch, max_wait_us, hbm_budget
+        h = ctypes.c_void_p()
+        _check(lib().rk_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._indices = []
+        self._cap = 1 << 16
+        self._ids = np.empty(self._cap, np.int32)
+        self._recs = (Completion * 4096)()
+
+    def add(self, index: "Index") -> int:
+        c = ctypes.c_int32()
+        _check(lib().rk_server_add_catalog(self._h, index._h, ctypes.byref(c)))
+        self._indices.append(index)
+        return c.value
+
+    def submit(self, catalog: int, q: np.ndarray, k: int, tag: int):
+        q = np.ascontiguousarray(q, np.float32)
+        _check(lib().rk_server_submit(self._h, int(catalog), _ptr(q), int(k), int(tag)))
+
+    def poll(self, wait_us: int = 0) -> list:
+        """Finished requests as (tag, catalog, status, ids, submit_ms, done_ms)."""
+        while True:
+            n = lib().rk_server_poll(self._h, self._recs, len(self._recs), _ptr(self._ids),
+                                     self._cap, int(wait_us))
+            if n >= 0:
+                break
+            msg = lib().rk_last_error().decode()
+            if "ids" not in msg:
+                raise RkError(RK_E_INVAL, msg)
+            self._cap *= 4  # the next result is larger than the id buffer
+            self._ids = np.empty(self._cap, np.int32)
+        out = []
+        for i in range(n):
+            r = self._recs[i]
+            ids = self._ids[r.ids_offset:r.ids_offset + r.count].copy()
+            out.append((r.tag, r.catalog, r.status, ids, r.submit_ms, r.done_ms))
+        return out
+
+    def inflight(self) -> int:
+        return lib().rk_server_inflight(self._h)
+
+    def used_bytes(self) -> int:
+        return lib().rk_server_used_bytes(self._h)
+
+    def close(self):
+        if self._h:
+            lib().rk_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

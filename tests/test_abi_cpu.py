@@ -30,10 +30,14 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+STRUCTS = (("rk_build_opts", rkmips.BuildOpts), ("rk_stats", rkmips.Stats),
+           ("rk_server_opts", rkmips.ServerOpts), ("rk_completion", rkmips.Completion))
+
+
 def test_struct_layouts_match_the_c_compiler(tmp_path):
     # sizeof/offsetof as gcc lays out the header's structs vs the ctypes mirror
     lines = []
-    for cname, py in (("rk_build_opts", rkmips.BuildOpts), ("rk_stats", rkmips.Stats)):
+    for cname, py in STRUCTS:
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
             lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
@@ -44,7 +48,7 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
                                                   check=True).stdout.splitlines())
-    for cname, py in (("rk_build_opts", rkmips.BuildOpts), ("rk_stats", rkmips.Stats)):
+    for cname, py in STRUCTS:
         assert int(out[cname]) == ctypes.sizeof(py)
         for f, _ in py._fields_:
             assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, f
