@@ -40,6 +40,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark over the three serving catalogs (separate JSON line)")
+    ap.add_argument("--serve-requests", type=int, default=10_000)
+    ap.add_argument("--serve-warmup", type=int, default=1_000)
+    ap.add_argument("--serve-batch", type=int, default=1024)
     return ap.parse_args()
 
 
@@ -103,8 +108,131 @@ def cpu_baseline(w, ks, budget_s: float) -> dict:
                       f"{len(ks)} (q,k) queries of the same workload, {dt:.1f} s"}
 
 
+def serve_main(args):
+    """Serving form: three resident catalogs, one server with continuous
+    batching.  Requests: catalog uniform, query item drawn from that
+    catalog's P, k ~ U{1..k_max} (seeded).  First the closed-loop saturation
+    rate (every request queued at once), then open-loop Poisson arrivals at
+    fixed fractions of it; latency runs from a request's scheduled arrival
+    to its ids on the host."""
+    import torch
+
+    from paper_2110_07131_amd import datagen
+    from paper_2110_07131_amd.rkmips import Index, Server
+
+    assert torch.cuda.is_available(), "no HIP device"
+    names = ["serve_small", "serve_mid", "serve_large"]
+    cats, build = [], {}
+    for i, nm in enumerate(names):
+        c = datagen.CONFIGS[nm]
+        w = datagen.workload(c["n"], c["m"], c["d"], c["sigma"], 0, seed=i)
+        t0 = time.perf_counter()
+        idx = Index.build(w.Q, w.P, c["k_max"], precision=args.precision, lb_items=args.lb_items)
+        build[nm] = {"build_s": time.perf_counter() - t0, "index_bytes": idx.stats()["footprint_bytes"],
+                     "n": c["n"], "m": c["m"], "d": c["d"]}
+        cats.append((w, c["k_max"], idx))
+        print(f"[serve] catalog {nm}: n={c['n']} m={c['m']} d={c['d']} built in "
+              f"{build[nm]['build_s']:.2f} s", file=sys.stderr, flush=True)
+    srv = Server(max_batch=args.serve_batch)
+    ids = [srv.add(idx) for _, _, idx in cats]
+    rng = np.random.default_rng(12345)
+
+    def draw(n):
+        cat = rng.integers(0, len(cats), n).astype(np.int32)
+        qs, ks = [], np.empty(n, np.int32)
+        for i in range(n):
+            w, kmax, _ = cats[cat[i]]
+            qs.append(w.P[int(rng.integers(len(w.P)))])
+            ks[i] = int(rng.integers(1, kmax + 1))
+        return cat, qs, ks
+
+    tag_base = [0]
+
+    def run(cat, qs, ks, arrivals=None):
+        """Submit (all at once, or at the scheduled arrivals) and wait for
+        every result; returns per-request (catalog, latency ms) and the span."""
+        n = len(ks)
+        tags = np.arange(tag_base[0], tag_base[0] + n, dtype=np.int64)
+        tag_base[0] += n
+        lat = np.empty(n)
+        first, last = None, 0.0
+        got = 0
+        if arrivals is None:
+            srv.submit_many(cat, qs, ks, tags)
+            first = srv.now_ms()
+        else:
+            i = 0
+            first = arrivals[0]
+            while i < n:
+                now = srv.now_ms()
+                j = int(np.searchsorted(arrivals, now, side="right"))
+                if j > i:
+                    srv.submit_many(cat[i:j], qs[i:j], ks[i:j], tags[i:j], arrivals[i:j])
+                    i = j
+                for tag, c, st, r, t_sub, t_done in srv.poll():
+                    assert st == 0
+                    lat[tag - tags[0]] = t_done - t_sub
+                    last = max(last, t_done)
+                    got += 1
+                if j == i and i < n:
+                    time.sleep(max(0.0, min(arrivals[i] - srv.now_ms(), 1.0)) / 1e3)
+        while got < n:
+            for tag, c, st, r, t_sub, t_done in srv.poll(wait_us=2000):
+                assert st == 0
+                lat[tag - tags[0]] = t_done - t_sub
+                last = max(last, t_done)
+                got += 1
+        return lat, last - first
+
+    cat, qs, ks = draw(args.serve_warmup)
+    run(cat, qs, ks)
+    n_sat = max(args.serve_requests, 2 * args.serve_batch * len(cats))
+    cat, qs, ks = draw(n_sat)
+    lat, span = run(cat, qs, ks)
+    sat_qps = n_sat / (span / 1e3)
+    print(f"[serve] closed loop: {n_sat} requests in {span:.1f} ms, {sat_qps:.0f} queries/s",
+          file=sys.stderr, flush=True)
+    loads = []
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        lam = frac * sat_qps
+        ntot = args.serve_warmup + args.serve_requests
+        cat, qs, ks = draw(ntot)
+        gaps = rng.exponential(1e3 / lam, ntot)
+        arrivals = srv.now_ms() + 1.0 + np.cumsum(gaps)
+        lat, span = run(cat, qs, ks, arrivals)
+        m = slice(args.serve_warmup, ntot)
+        L, C = lat[m], cat[m]
+        per = {names[c]: {"p50_ms": float(np.percentile(L[C == c], 50)),
+                          "p99_ms": float(np.percentile(L[C == c], 99)), "requests": int((C == c).sum())}
+               for c in range(len(cats))}
+        loads.append({"load": frac, "offered_qps": lam,
+                      "achieved_qps": ntot / (span / 1e3),
+                      "p50_ms": float(np.percentile(L, 50)), "p99_ms": float(np.percentile(L, 99)),
+                      "per_catalog": per})
+        print(f"[serve] load {frac}: offered {lam:.0f}/s, p50 {loads[-1]['p50_ms']:.3f} ms, "
+              f"p99 {loads[-1]['p99_ms']:.3f} ms", file=sys.stderr, flush=True)
+    line = {
+        "metric": "reverse k-MIPS serving latency (exact sets), p50/p99 from arrival to ids on host",
+        "unit": "ms", "n_gpus": 1, "dtype": args.precision.replace("fp", "f"), "data": "synthetic",
+        "config": {"workload": "serving: catalogs (50k,10k,d50), (500k,50k,d100), (2M,100k,d200), "
+                               "sigma 0.5, k_max 25; catalog uniform, query item from its P, "
+                               "k ~ U{1..25}; Poisson arrivals",
+                   "max_batch": args.serve_batch, "lb_items": args.lb_items or "m",
+                   "requests_per_load": args.serve_requests, "warmup": args.serve_warmup},
+        "saturation_qps": sat_qps, "loads": loads, "catalogs": build,
+        "server_device_bytes": srv.used_bytes(),
+    }
+    print(json.dumps(line))
+    srv.close()
+
+
 def main():
     args = parse()
+    if args.serve:
+        if args.gpus != 1:
+            print("the serving benchmark runs on one GPU", file=sys.stderr)
+            sys.exit(2)
+        return serve_main(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has "
               f"no multi-GPU path", file=sys.stderr)

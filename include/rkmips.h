@@ -227,10 +227,11 @@ const char *rk_last_error(void);
 /* ------------------------------------------------------------------------
  * Serving: the online phase (Algorithm 3; Theorem 2 bounds its cost per
  * query) under a stream of single-query requests over several resident
- * catalogs.  A server owns one worker thread that batches the pending
- * requests of a catalog continuously (whatever is queued when the device
- * becomes free, up to max_batch) and runs them through the batched path of
- * that catalog's index; results come back to the host per request.
+ * catalogs.  Every catalog has a batching thread and a HIP stream of its
+ * own: the thread batches the catalog's pending requests continuously
+ * (whatever is queued when its previous launch has finished, up to
+ * max_batch) and runs them through the batched path of the catalog's index;
+ * results come back to the host per request.  Catalogs run concurrently.
  *
  * Catalogs are admitted by device-memory footprint: the index's own bytes
  * plus the batch workspace and the server's buffers for max_batch queries
@@ -276,6 +277,18 @@ rk_status rk_server_add_catalog(rk_server *s, rk_index *idx, int32_t *catalog);
  * k_max (no rebuild while serving). */
 rk_status rk_server_submit(rk_server *s, int32_t catalog, const float *q, int32_t k,
                            int64_t tag);
+
+/* Queue n queries at once, with the checks of rk_server_submit (all or
+ * nothing).  q[i] points to the d floats of query i's catalog.  arrival_ms
+ * (or NULL: now) is each request's arrival on the server clock, the time its
+ * latency counts from: an open-loop load generator that submits late passes
+ * the scheduled times (later than now counts as now). */
+rk_status rk_server_submit_many(rk_server *s, int64_t n, const int32_t *catalog,
+                                const float *const *q, const int32_t *k, const int64_t *tag,
+                                const double *arrival_ms);
+
+/* The server clock: ms since rk_server_create. */
+double rk_server_now_ms(rk_server *s);
 
 /* Move up to max_out finished requests out of the server, oldest first:
  * their records to out[], their ids one after another into ids[0..ids_cap).

@@ -678,6 +678,8 @@ struct ServerCatalog {
   int64_t* offs_pin = nullptr;
   int32_t* ids_pin = nullptr;
   int64_t bytes = 0;  // device bytes charged to the budget
+  std::condition_variable cv;  // requests queued (or the server stops)
+  std::thread worker;          // this catalog's batching thread
 };
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -720,19 +722,12 @@ struct rk_server {
   std::chrono::steady_clock::time_point t0;
   std::vector<ServerCatalog*> cats;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_done;
   std::deque<ServerDone> done;
   int64_t inflight = 0;
   int64_t used = 0;
   int64_t budget = 0;
   bool stop = false;
-  std::thread worker;
-
-  bool pending() const {
-    for (const ServerCatalog* c : cats)
-      if (!c->queue.empty()) return true;
-    return false;
-  }
 
   // One launch for the queued requests of catalog c, results to the host.
   void run_batch(int32_t ci, ServerCatalog* c, std::vector<ServerReq>& batch) {
@@ -786,32 +781,24 @@ struct rk_server {
     cv_done.notify_all();
   }
 
-  void loop() {
+  // Batching thread of catalog ci: every catalog has its own thread and
+  // stream, so catalogs run concurrently and a small catalog's requests do
+  // not wait behind a large catalog's launch.
+  void loop(int32_t ci, ServerCatalog* c) {
     (void)hipSetDevice(opts.device);
-    size_t rr = 0;
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-      cv_work.wait(lk, [&] { return stop || pending(); });
-      if (!pending()) {
+      c->cv.wait(lk, [&] { return stop || !c->queue.empty(); });
+      if (c->queue.empty()) {
         if (stop) break;
         continue;
       }
-      int32_t ci = 0;
-      for (size_t j = 0; j < cats.size(); ++j) {
-        const size_t c = (rr + j) % cats.size();
-        if (!cats[c]->queue.empty()) {
-          ci = (int32_t)c;
-          break;
-        }
-      }
-      rr = (size_t)ci + 1;
-      ServerCatalog* c = cats[ci];
       if (opts.max_wait_us > 0) {
         const double deadline = c->queue.front().t_submit + opts.max_wait_us / 1000.0;
         while (!stop && (int64_t)c->queue.size() < opts.max_batch) {
           const double left = deadline - ms_since(t0);
           if (left <= 0) break;
-          cv_work.wait_for(lk, std::chrono::duration<double, std::milli>(left));
+          c->cv.wait_for(lk, std::chrono::duration<double, std::milli>(left));
         }
       }
       const int64_t nb = std::min<int64_t>((int64_t)c->queue.size(), opts.max_batch);
@@ -832,8 +819,9 @@ struct rk_server {
       std::lock_guard<std::mutex> lk(mu);
       stop = true;
     }
-    cv_work.notify_all();
-    if (worker.joinable()) worker.join();
+    for (ServerCatalog* c : cats) c->cv.notify_all();
+    for (ServerCatalog* c : cats)
+      if (c->worker.joinable()) c->worker.join();
     (void)hipSetDevice(opts.device);
     for (ServerCatalog* c : cats) {
       if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -1143,7 +1131,6 @@ rk_status rk_server_create(const rk_server_opts* opts, rk_server** out) {
   s->opts = o;
   s->budget = budget;
   s->t0 = std::chrono::steady_clock::now();
-  s->worker = std::thread([s] { s->loop(); });
   *out = s;
   return RK_OK;
 }
@@ -1192,8 +1179,10 @@ rk_status rk_server_add_catalog(rk_server* s, rk_index* h, int32_t* catalog) {
   if (e != hipSuccess)
     return undo(fail(e == hipErrorOutOfMemory ? RK_E_NOMEM : RK_E_DEVICE, hipGetErrorString(e)));
   std::lock_guard<std::mutex> lk(s->mu);
-  *catalog = (int32_t)s->cats.size();
+  const int32_t ci = (int32_t)s->cats.size();
+  *catalog = ci;
   s->cats.push_back(c);
+  c->worker = std::thread([s, ci, c] { s->loop(ci, c); });
   return RK_OK;
 }
 
@@ -1217,10 +1206,48 @@ rk_status rk_server_submit(rk_server* s, int32_t catalog, const float* q, int32_
     r.t_submit = ms_since(s->t0);
     s->cats[catalog]->queue.push_back(std::move(r));
     ++s->inflight;
+    s->cats[catalog]->cv.notify_one();
   }
-  s->cv_work.notify_one();
   return RK_OK;
 }
+
+rk_status rk_server_submit_many(rk_server* s, int64_t n, const int32_t* catalog,
+                                const float* const* q, const int32_t* k, const int64_t* tag,
+                                const double* arrival_ms) {
+  if (!s || n < 0 || (n > 0 && (!catalog || !q || !k || !tag)))
+    return fail(RK_E_INVAL, "NULL argument or negative size");
+  std::vector<ServerReq> rs(n);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int64_t i = 0; i < n; ++i) {
+      if (catalog[i] < 0 || catalog[i] >= (int32_t)s->cats.size() || !q[i])
+        return fail(RK_E_INVAL, "request " + std::to_string(i) + ": no such catalog or NULL query");
+      const rk_index* h = s->cats[catalog[i]]->idx;
+      if (k[i] < 1) return fail(RK_E_INVAL, "request " + std::to_string(i) + ": k must be >= 1");
+      if (k[i] > h->ix.kmax) return fail(RK_E_KMAX, "request " + std::to_string(i) + ": k > k_max");
+      rs[i].q.assign(q[i], q[i] + h->ix.d);
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (!host_values_ok(rs[i].q.data(), (int64_t)rs[i].q.size()))
+      return fail(RK_E_INVAL, "request " + std::to_string(i) + ": a non-finite value or |x| >= 2^40");
+    rs[i].k = k[i];
+    rs[i].tag = tag[i];
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    const double now = ms_since(s->t0);
+    for (int64_t i = 0; i < n; ++i) {
+      rs[i].t_submit = arrival_ms ? std::min(arrival_ms[i], now) : now;
+      s->cats[catalog[i]]->queue.push_back(std::move(rs[i]));
+    }
+    s->inflight += n;
+    for (int64_t i = 0; i < n; ++i) s->cats[catalog[i]]->cv.notify_one();
+  }
+  return RK_OK;
+}
+
+double rk_server_now_ms(rk_server* s) { return s ? ms_since(s->t0) : -1.0; }
 
 int64_t rk_server_poll(rk_server* s, rk_completion* out, int64_t max_out, int32_t* ids,
                        int64_t ids_cap, int32_t wait_us) {

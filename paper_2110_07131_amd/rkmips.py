@@ -31,6 +31,7 @@ EXPORTS = [
     "rk_index_free", "rk_last_error",
     "rk_server_opts_default", "rk_server_create", "rk_server_add_catalog", "rk_server_submit",
     "rk_server_poll", "rk_server_inflight", "rk_server_used_bytes", "rk_server_free",
+    "rk_server_submit_many", "rk_server_now_ms",
 ]
 
 
@@ -154,6 +155,10 @@ def lib():
     L.rk_server_used_bytes.restype = i64
     L.rk_server_free.argtypes = [vp]
     L.rk_server_free.restype = None
+    L.rk_server_submit_many.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    L.rk_server_submit_many.restype = ctypes.c_int
+    L.rk_server_now_ms.argtypes = [vp]
+    L.rk_server_now_ms.restype = f64
     _lib = L
     return L
 
@@ -353,6 +358,22 @@ class Server:
     def submit(self, catalog: int, q: np.ndarray, k: int, tag: int):
         q = np.ascontiguousarray(q, np.float32)
         _check(lib().rk_server_submit(self._h, int(catalog), _ptr(q), int(k), int(tag)))
+
+    def submit_many(self, catalogs, queries, ks, tags, arrival_ms=None):
+        """Queue many requests in one call; queries is a list of float32 rows
+        (kept alive by the caller until the call returns)."""
+        n = len(ks)
+        cat = np.ascontiguousarray(catalogs, np.int32)
+        kk = np.ascontiguousarray(ks, np.int32)
+        tg = np.ascontiguousarray(tags, np.int64)
+        rows = [np.ascontiguousarray(q, np.float32) for q in queries]
+        ptrs = (ctypes.c_void_p * max(n, 1))(*[r.ctypes.data for r in rows])
+        arr = None if arrival_ms is None else np.ascontiguousarray(arrival_ms, np.float64)
+        _check(lib().rk_server_submit_many(self._h, n, _ptr(cat), ptrs, _ptr(kk), _ptr(tg),
+                                           _ptr(arr) if arr is not None else None))
+
+    def now_ms(self) -> float:
+        return lib().rk_server_now_ms(self._h)
 
     def poll(self, wait_us: int = 0) -> list:
         """Finished requests as (tag, catalog, status, ids, submit_ms, done_ms)."""
