@@ -50,7 +50,7 @@ def parse():
 
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 KERNEL_NAMES = {"filter": "k_filter", "batch_filter": "k_bfilter", "batch_pairs": "k_brecheck_exact/k_bscan",
-                "batch_assemble": "k_bscan+k_bassemble", "batch_prep": "k_bnorms+k_bsort+k_btile",
+                "batch_assemble": "k_boffsets+k_bassemble", "batch_prep": "k_bnorms+k_bsort+k_btile",
                 "recheck": "k_recheck", "finalize": "k_finalize", "verify": "k_verify"}
 
 

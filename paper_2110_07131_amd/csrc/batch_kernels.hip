@@ -1025,7 +1025,7 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
 // CSR assembly.  Offsets: one workgroup scans the chunk's counts (original
 // chunk order) starting from *base.  Ids: one workgroup per query turns its
 // bitmap row into ascending ids, then clears the row and the count.
-__global__ void __launch_bounds__(1024) k_bscan(const unsigned long long* __restrict__ counts,
+__global__ void __launch_bounds__(1024) k_boffsets(const unsigned long long* __restrict__ counts,
                                                 const uint8_t* __restrict__ all, int64_t n,
                                                 int32_t nq, const int64_t* __restrict__ base,
                                                 int64_t* __restrict__ offs) {
@@ -1184,7 +1184,7 @@ void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
 
 void launch_bassemble(const BatchView& bv, int32_t nq, const int64_t* base, int64_t* offs,
                       int32_t* ids, int64_t cap, hipStream_t s) {
-  hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, s, bv.counts, bv.all, bv.n, nq, base, offs);
+  hipLaunchKernelGGL(k_boffsets, dim3(1), dim3(1024), 0, s, bv.counts, bv.all, bv.n, nq, base, offs);
   hipLaunchKernelGGL(k_bassemble, dim3(nq), dim3(256), 0, s, bv, offs, ids, cap);
 }
 
