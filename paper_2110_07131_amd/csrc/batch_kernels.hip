@@ -39,98 +39,68 @@ __global__ void k_bnorms(const float* __restrict__ qs, int32_t nq, int32_t d,
   if (lane == 0) qn[j] = f32_up(sqrt(s) * (1.0 + (double)(d + 4) * 0x1p-53));
 }
 
-// Sort of the chunk's queries by (k ascending, |q| descending, index), so
-// that a 64-query tile usually has one k and queries of similar norm: the
-// Lemma 3 test then prunes whole tiles and the epilogue reads one lower
-// bound per user.  One workgroup, bitonic network over N = 2^p <= 4096 keys;
-// thread t holds positions t + 1024 e.  Exchanges at stride >= 1024 are in
-// registers, 64..512 through LDS, < 64 by lane shuffles.
-__device__ __forceinline__ bool key_less(unsigned long long ka, int32_t ia, unsigned long long kb,
-                                         int32_t ib) {
-  return ka < kb || (ka == kb && ia < ib);
-}
+// Sort of the chunk's queries by k ascending, then |q| descending in buckets
+// of 1/16 octave below the chunk's largest norm (64 buckets per k), so that a
+// 64-query tile usually has one k and queries of similar norm: the Lemma 3
+// test then prunes whole tiles and the epilogue reads one lower bound per
+// user.  Counting sort in one workgroup (histogram, scan, scatter); the order
+// inside a bucket is the atomics' order, which no result depends on (every
+// decision is per (user, query)).
+constexpr int kSortBuckets = 64;
 
 __global__ void __launch_bounds__(1024) k_bsort(const float* __restrict__ qn,
                                                 const int32_t* __restrict__ ks, int32_t nq,
-                                                int32_t* __restrict__ perm) {
-  __shared__ unsigned long long sk[kBatchChunkMax];
-  __shared__ int32_t si[kBatchChunkMax];
-  const int t = threadIdx.x;
-  int N = 64;
-  while (N < nq) N <<= 1;
-  const int E = N > 1024 ? N / 1024 : 1;  // elements per thread (1, 2 or 4)
-  const bool active = t < N;              // N < 1024: only the first N threads
-  unsigned long long key[4];
-  int32_t id[4];
+                                                int32_t kmax, int32_t* __restrict__ perm) {
+  extern __shared__ int hist[];  // (kmax + 1) * kSortBuckets bins
+  __shared__ uint32_t top_bits;
+  __shared__ int wsum[16];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int nbins = (kmax + 1) * kSortBuckets;
+  if (t == 0) top_bits = 0u;
+  for (int i = t; i < nbins; i += 1024) hist[i] = 0;
+  __syncthreads();
+  uint32_t mx = 0u;  // norms are >= 0: larger float bits = larger norm
+  for (int p = t; p < nq; p += 1024) mx = max(mx, __float_as_uint(qn[p]));
+  for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+  if (lane == 0) atomicMax(&top_bits, mx);
+  __syncthreads();
+  const uint32_t top = top_bits;
+  int key[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int p = t + 1024 * e;
-    if (e < E && p < nq) {
-      // k ascending, then norm descending (norms are >= 0: larger float bits = larger)
-      key[e] = ((unsigned long long)(uint32_t)ks[p] << 32) | (uint32_t)(~__float_as_uint(qn[p]));
-      id[e] = p;
-    } else {
-      key[e] = ~0ull;
-      id[e] = INT32_MAX;
+    key[e] = -1;
+    if (p < nq) {
+      const int k = min(max(ks[p], 0), kmax);
+      const uint32_t bk = min((top - __float_as_uint(qn[p])) >> 19, (uint32_t)(kSortBuckets - 1));
+      key[e] = k * kSortBuckets + (int)bk;
+      atomicAdd(&hist[key[e]], 1);
     }
   }
-  for (int size = 2; size <= N; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      if (stride >= 1024) {
-        const int es = stride / 1024;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int f = e ^ es;
-          if (e < E && f > e && f < 4) {
-            const int p = t + 1024 * e;
-            const bool asc = (p & size) == 0;
-            const bool swap = asc ? key_less(key[f], id[f], key[e], id[e])
-                                  : key_less(key[e], id[e], key[f], id[f]);
-            if (swap) {
-              unsigned long long tk = key[e]; key[e] = key[f]; key[f] = tk;
-              int32_t ti = id[e]; id[e] = id[f]; id[f] = ti;
-            }
-          }
-        }
-      } else if (stride >= 64) {
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (e < E && active) { sk[t + 1024 * e] = key[e]; si[t + 1024 * e] = id[e]; }
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (e < E && active) {
-            const int p = t + 1024 * e, q = p ^ stride;
-            const unsigned long long ko = sk[q];
-            const int32_t io = si[q];
-            const bool asc = (p & size) == 0;
-            const bool take_min = asc == (p < q);
-            const bool other_less = key_less(ko, io, key[e], id[e]);
-            if (take_min == other_less) { key[e] = ko; id[e] = io; }
-          }
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (e < E) {
-            const int p = t + 1024 * e, q = p ^ stride;
-            const unsigned long long ko = __shfl_xor(key[e], stride);
-            const int32_t io = __shfl_xor(id[e], stride);
-            const bool asc = (p & size) == 0;
-            const bool take_min = asc == (p < q);
-            const bool other_less = key_less(ko, io, key[e], id[e]);
-            if (active && take_min == other_less) { key[e] = ko; id[e] = io; }
-          }
-        }
-      }
-    }
+  __syncthreads();
+  // exclusive scan of the bins: thread t owns bins [t*per, (t+1)*per)
+  const int per = (nbins + 1023) / 1024;
+  const int b0 = min(t * per, nbins), b1 = min(b0 + per, nbins);
+  int local = 0;
+  for (int i = b0; i < b1; ++i) local += hist[i];
+  int incl = local;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
   }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int p = t + 1024 * e;
-    if (e < E && active && p < nq) perm[p] = id[e];
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int run = incl - local;
+  for (int w = 0; w < wave; ++w) run += wsum[w];
+  for (int i = b0; i < b1; ++i) {
+    const int cnt = hist[i];
+    hist[i] = run;
+    run += cnt;
   }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (key[e] >= 0) perm[atomicAdd(&hist[key[e]], 1)] = t + 1024 * e;
 }
 
 // Query tiles in sorted order: fp32 [T][d][64] and (bf16 mode) [T][G][64][8],
@@ -1049,51 +1019,65 @@ __global__ void __launch_bounds__(1024) k_boffsets(const unsigned long long* __r
   }
 }
 
-__global__ void __launch_bounds__(256) k_bassemble(BatchView bv, const int64_t* __restrict__ offs,
+__global__ void __launch_bounds__(256) k_bassemble(BatchView bv, int32_t nq,
+                                                   const int64_t* __restrict__ offs,
                                                    int32_t* __restrict__ ids, int64_t cap) {
-  // Each wave owns a contiguous quarter of the query's bitmap row; lanes read
-  // consecutive words (coalesced).  Pass 1 counts the quarter, pass 2 writes
-  // ids with a wave-wide inclusive scan of per-word counts.
-  __shared__ int64_t wbase[4];
-  const int32_t j = blockIdx.x;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // One wave per query, one pass over its bitmap row (W words, a multiple of
+  // 4): lane L reads words 4(v0+L)..+3 of each 256-word group, so ids come
+  // out ascending; groups without a bit cost one load and a ballot.  Words
+  // that held bits are cleared.
+  const int lane = threadIdx.x & 63;
+  const int32_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nq) return;
   if (bv.all[j]) {  // k > m: every user, ascending
     const int64_t b0 = offs[j];
-    for (int64_t i = t; i < bv.n && b0 + i < cap; i += blockDim.x) ids[b0 + i] = (int32_t)i;
-    if (t == 0 && bv.ctr) atomicAdd(&bv.ctr[C_RES], (unsigned long long)bv.n);
+    for (int64_t i = lane; i < bv.n && b0 + i < cap; i += 64) ids[b0 + i] = (int32_t)i;
+    if (lane == 0 && bv.ctr) atomicAdd(&bv.ctr[C_RES], (unsigned long long)bv.n);
     return;
   }
-  uint32_t* row = bv.bits + (int64_t)j * bv.W;
-  const int64_t w0 = bv.W * wave / 4, w1 = bv.W * (wave + 1) / 4;
-  int c = 0;
-  for (int64_t w = w0 + lane; w < w1; w += 64) c += __popc(row[w]);
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-  if (lane == 0) wbase[wave] = c;
-  __syncthreads();
-  int64_t pos = offs[j];
-  for (int i = 0; i < wave; ++i) pos += wbase[i];
-  const int64_t total = wbase[0] + wbase[1] + wbase[2] + wbase[3];
-  for (int64_t wb = w0; wb < w1; wb += 64) {
-    const int64_t w = wb + lane;
-    uint32_t bits = w < w1 ? row[w] : 0u;
-    const int pc = __popc(bits);
-    int incl = pc;
-    for (int off = 1; off < 64; off <<= 1) {
-      const int v = __shfl_up(incl, off);
-      if (lane >= off) incl += v;
+  u32x4* row = (u32x4*)(bv.bits + (int64_t)j * bv.W);
+  const int64_t nv = bv.W / 4;
+  const int64_t start = offs[j];
+  int64_t pos = start;
+  constexpr int G = 4;  // groups loaded together (independent loads in flight)
+  for (int64_t v00 = 0; v00 < nv; v00 += 64 * G) {
+    u32x4 xs[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t v = v00 + 64 * g + lane;
+      xs[g] = u32x4{0u, 0u, 0u, 0u};
+      if (v < nv) xs[g] = row[v];
     }
-    int64_t p = pos + incl - pc;
-    if (bits) row[w] = 0u;
-    while (bits) {
-      const int b = __ffs(bits) - 1;
-      bits &= bits - 1;
-      if (p < cap) ids[p] = (int32_t)(w * 32 + b);
-      ++p;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t v = v00 + 64 * g + lane;
+      const u32x4 x = xs[g];
+      const int c = __popc(x[0]) + __popc(x[1]) + __popc(x[2]) + __popc(x[3]);
+      if (__ballot(c != 0) == 0ull) continue;
+      int incl = c;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+      }
+      int64_t p = pos + incl - c;
+      if (c) {
+        row[v] = u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          uint32_t bits = x[q];
+          while (bits) {
+            const int b = __ffs(bits) - 1;
+            bits &= bits - 1;
+            if (p < cap) ids[p] = (int32_t)((4 * v + q) * 32 + b);
+            ++p;
+          }
+        }
+      }
+      pos += __shfl(incl, 63);
     }
-    pos += __shfl(incl, 63);
   }
-  if (t == 0) {
-    if (bv.ctr) atomicAdd(&bv.ctr[C_RES], (unsigned long long)total);
+  if (lane == 0) {
+    if (bv.ctr) atomicAdd(&bv.ctr[C_RES], (unsigned long long)(pos - start));
     bv.counts[j] = 0ull;
   }
 }
@@ -1113,7 +1097,8 @@ void launch_bprep(const DevIndex& ix, const BatchView& bv, const int32_t* ks_dev
   if (!ix.exact && ix.nB > 0)
     hipLaunchKernelGGL(k_bclear, dim3((ix.nB + 255) / 256), dim3(256), 0, s, bv.bcnt, ix.nB,
                        bv.nchunks);
-  hipLaunchKernelGGL(k_bsort, dim3(1), dim3(1024), 0, s, bv.qn, ks_dev, nq, bv.perm);
+  hipLaunchKernelGGL(k_bsort, dim3(1), dim3(1024), (size_t)(ix.kmax + 1) * kSortBuckets * 4, s,
+                     bv.qn, ks_dev, nq, ix.kmax, bv.perm);
   dim3 blk(64, 4);
   hipLaunchKernelGGL(k_btile, dim3((bv.nq_pad + 3) / 4), blk, 0, s, bv.qs, ks_dev, bv.qn,
                      bv.perm, nq, bv.nq_pad, ix.d, ix.d16, ix.m, bv.qt, ix.bf16 ? bv.qb : nullptr,
@@ -1185,7 +1170,7 @@ void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
 void launch_bassemble(const BatchView& bv, int32_t nq, const int64_t* base, int64_t* offs,
                       int32_t* ids, int64_t cap, hipStream_t s) {
   hipLaunchKernelGGL(k_boffsets, dim3(1), dim3(1024), 0, s, bv.counts, bv.all, bv.n, nq, base, offs);
-  hipLaunchKernelGGL(k_bassemble, dim3(nq), dim3(256), 0, s, bv, offs, ids, cap);
+  hipLaunchKernelGGL(k_bassemble, dim3((nq + 3) / 4), dim3(256), 0, s, bv, nq, offs, ids, cap);
 }
 
 }  // namespace rk

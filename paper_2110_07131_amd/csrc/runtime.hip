@@ -42,6 +42,9 @@ constexpr int32_t kMaxKmax = 128;
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// Words of a batched result bitmap row: one bit per user, rows 16-byte aligned.
+int64_t bitmap_words(int64_t n) { return round_up(std::max<int64_t>((n + 31) / 32, 1), 4); }
+
 double gamma_(double k, double u) { return k * u / (1.0 - k * u); }
 
 // Rigorous relative bounds |approx u.x - f(x,u)| <= eps * |u| |x| (see the
@@ -500,7 +503,7 @@ struct BatchSizes {
 BatchSizes batch_sizes(const rk_index* h, int32_t chunk) {
   const DevIndex& ix = h->ix;
   BatchSizes z;
-  const int64_t cp = round_up(chunk, TILE), W = std::max<int64_t>((ix.n + 31) / 32, 1);
+  const int64_t cp = round_up(chunk, TILE), W = bitmap_words(ix.n);
   int64_t pc = std::min<int64_t>((int64_t)chunk * std::max<int64_t>(ix.n_pad, 1),
                                  ix.exact ? kPairBudgetExact : kPairBudget);
   if (h->opts.pair_cap > 0) pc = h->opts.pair_cap;
@@ -527,7 +530,7 @@ BatchSizes batch_sizes(const rk_index* h, int32_t chunk) {
 
 // Queries per chunk of the batched path for a batch of nq queries.
 int32_t batch_chunk(const rk_index* h, int64_t nq) {
-  const int64_t W = std::max<int64_t>((h->ix.n + 31) / 32, 1);
+  const int64_t W = bitmap_words(h->ix.n);
   return (int32_t)std::max<int64_t>(
       1, std::min<int64_t>({nq, (int64_t)kBatchChunkMax, kBitmapBudget / (W * 4)}));
 }
@@ -545,7 +548,7 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
   b.pair_st = b.cfill = b.nchunks = b.bcnt = b.bchunks = nullptr;
   const DevIndex& ix = h->ix;
   const BatchSizes z = batch_sizes(h, chunk);
-  const int64_t cp = round_up(chunk, TILE), W = (ix.n + 31) / 32;
+  const int64_t cp = round_up(chunk, TILE), W = bitmap_words(ix.n);
   const int64_t pc = z.pc;
   b.qcap = 0;
   HIPTRY(h->dalloc(&b.qn, chunk));
@@ -619,7 +622,7 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
     }
     return RK_OK;
   }
-  const int64_t W = std::max<int64_t>((ix.n + 31) / 32, 1);
+  const int64_t W = bitmap_words(ix.n);
   const int32_t chunk = batch_chunk(h, nq);
   rk_status st = ensure_batch_ws(h, chunk);
   if (st != RK_OK) return st;
