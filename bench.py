@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first run 3 plain device copies of this many MiB (counter calibration)")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark over the three serving catalogs (separate JSON line)")
     ap.add_argument("--serve-requests", type=int, default=10_000)
@@ -90,6 +92,20 @@ def dominant_roofline(cls: str, times, st: dict, d: int, precision: str) -> dict
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "avg_launch_us": avg_s * 1e6, "launches_per_step": launches,
             "algorithmic_bytes_per_launch": nbytes, "traffic": None}
+
+
+def measured_traffic(kernel: str, key: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    there is none or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2110_07131_amd.profiling import source_hash
+    with open(path) as fh:
+        e = json.load(fh).get(f"{kernel}:{key}")
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(w, ks, budget_s: float) -> dict:
@@ -244,6 +260,14 @@ def main():
 
     assert torch.cuda.is_available(), "no HIP device"
     torch.cuda.set_device(0)
+    if args.calib_copy_mb > 0:  # plain copies of a known size (counter calibration)
+        n = (args.calib_copy_mb << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = datagen.CONFIGS[args.config]
     w = datagen.config_workload(args.config)
     n, m, d, kmax = cfg["n"], cfg["m"], cfg["d"], cfg["k_max"]
@@ -308,6 +332,8 @@ def main():
     idx.set_timing(0)
     dom = max(kt, key=lambda c: kt[c][0])
     roofline = dominant_roofline(dom, kt[dom], st, d, args.precision)
+    table = "exact" if (args.lb_items == 0 or args.lb_items >= m) else f"lb{args.lb_items}"
+    roofline["traffic"] = measured_traffic(roofline["kernel"], f"{args.config}/{args.precision}/{table}")
     kernel_share = {c: {"ms_per_step": v[0], "launches": v[1]} for c, v in kt.items()}
 
     lat = None

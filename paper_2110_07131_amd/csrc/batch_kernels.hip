@@ -362,8 +362,6 @@ __global__ void __launch_bounds__(256, 2) k_bfilter(DevIndex ix, BatchView bv) {
                            ((hm >> 12) & 0xF000u);
     const int ucol = uh * 32 + col;
     uint32_t rest = 0;
-    float ev[16];
-    int kv[16];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int rb = quarter_row(qhalf, half, g * 4);
@@ -374,19 +372,28 @@ __global__ void __launch_bounds__(256, 2) k_bfilter(DevIndex ix, BatchView bv) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = g * 4 + i;
-        kv[r] = max(kks[i], 1);
-        ev[r] = fmaf(a_u, nqs[i], ix.eps_abs);
-        const float L = Ll[(kv[r] - 1) * TILE + ucol];
-        rest |= (uint32_t)!(acc[r] + ev[r] < L) << r;
+        const float ev = fmaf(a_u, nqs[i], ix.eps_abs);
+        const float L = Ll[(max(kks[i], 1) - 1) * TILE + ucol];
+        rest |= (uint32_t)!(acc[r] + ev < L) << r;
       }
     }
     rest &= valid ? cells : 0u;
     uint32_t yes = 0;
-    if (__ballot(rest != 0u)) {
+    if (__ballot(rest != 0u)) {  // some pair Lemma 1 did not reject: the "yes" test
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float Y = Yl[(kv[r] - 1) * TILE + ucol];
-        yes |= (uint32_t)(acc[r] - ev[r] >= Y) << r;
+      for (int g = 0; g < 4; ++g) {
+        const int rb = quarter_row(qhalf, half, g * 4);
+        const float4 n4 = *(const float4*)(meta_n + rb);
+        const int4 k4 = *(const int4*)(meta_k + rb);
+        const float nqs[4] = {n4.x, n4.y, n4.z, n4.w};
+        const int kks[4] = {k4.x, k4.y, k4.z, k4.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = g * 4 + i;
+          const float ev = fmaf(a_u, nqs[i], ix.eps_abs);
+          const float Y = Yl[(max(kks[i], 1) - 1) * TILE + ucol];
+          yes |= (uint32_t)(acc[r] - ev >= Y) << r;
+        }
       }
       yes &= rest;
     }
