@@ -181,9 +181,11 @@ void launch_filter(const DevIndex& ix, const float* q, int32_t k, const QueryWS&
 // = item of the current 64-item tile.  Counts the items certified to beat q
 // (Corollary 2: k of them decide "no") and stops at the first item whose
 // Cauchy-Schwarz bound cannot exceed u.q (Corollary 1: nothing after it can
-// beat q).  Items whose comparison is inside the margin are counted apart:
-// the user is "yes" only when even all of them together stay below k, else
-// it goes to the float64 recheck.
+// beat q).  Items whose comparison is inside the margin are compared in
+// float64 right there (f(p,u) against f(q,u), both in the definition's
+// order; the item equal to q of a query taken from P is one of them), so
+// every item's verdict is exact: "no" once k items beat q, "yes" at the
+// Corollary 1 limit.
 template <bool BF16>
 __global__ void __launch_bounds__(256) k_verify(DevIndex ix, const float* __restrict__ q,
                                                 int32_t k, QueryWS ws) {
@@ -206,7 +208,10 @@ __global__ void __launch_bounds__(256) k_verify(DevIndex ix, const float* __rest
       else lo = mid + 1;
     }
     const int64_t stop = lo;
-    int beats = 0, unsure = 0;
+    int beats = 0;
+    bool used64 = false;
+    double fq = 0.0;
+    const float* urow = ix.Qrow + r * ix.d;
     int64_t scanned = 0;
     const int64_t ub = r / TILE, ul = r % TILE;
     for (int64_t t0 = 0; t0 < stop && beats < k; t0 += TILE) {
@@ -246,23 +251,22 @@ __global__ void __launch_bounds__(256) k_verify(DevIndex ix, const float* __rest
       const bool beat = inb && (diff > tol);
       const bool unc = inb && !beat && !(diff <= -tol);
       beats += __popcll(__ballot(beat));
-      unsure += __popcll(__ballot(unc));
+      if (__ballot(unc)) {  // inside the margin: float64 for these items only
+        if (!used64) fq = dot64_rows(q, urow, ix.d);
+        used64 = true;
+        const bool b64 = unc && dot64_rows(ix.Prow + j * ix.d, urow, ix.d) > fq;
+        beats += __popcll(__ballot(b64));
+      }
       scanned += (stop - t0 < TILE) ? (stop - t0) : TILE;
     }
-    int cls;
-    if (beats >= k) {
-      cls = RK_C_SCAN_NO;
-    } else if (beats + unsure < k) {
-      cls = RK_C_SCAN_YES;
-      if (lane == 0) set_result(ws, ix, r);
-    } else {
-      cls = 255;
-      if (lane == 0) ws.rchk_idx[atomicAdd(&ws.cnt[1], 1)] = (int32_t)r;
-    }
+    const bool yes = beats < k;
+    if (yes && lane == 0) set_result(ws, ix, r);
     if (lane == 0) {
-      if (cls != 255) trace(ws, ix, r, cls, NAN);
+      trace(ws, ix, r,
+            used64 ? (yes ? RK_C_RECHECK_YES : RK_C_RECHECK_NO) : (yes ? RK_C_SCAN_YES : RK_C_SCAN_NO),
+            NAN);
       ctr_add(ws, C_SCAN, (unsigned long long)scanned);
-      if (cls == 255) ctr_add(ws, C_RCHK, 1);
+      if (used64) ctr_add(ws, C_RCHK, 1);
     }
   }
 }
