@@ -103,7 +103,7 @@ def measured_traffic(kernel: str, key: str):
     from paper_2110_07131_amd.profiling import source_hash
     with open(path) as fh:
         e = json.load(fh).get(f"{kernel}:{key}")
-    if not e or e.get("source_hash") != source_hash():
+    if not e or e.get("source_hash") != source_hash(kernel):
         return None
     return e["traffic_bytes_per_launch"]
 

@@ -5,8 +5,8 @@ benchmark command (which also performs plain device copies of a known size,
 `bench.py --calib-copy-mb N`) give per-dispatch KiB for every kernel.  The
 copy dispatches calibrate each counter (bytes the copy must move / counter
 reading); the kernel's average reading times that factor is its HBM traffic
-per launch.  The result is stamped with a hash of the kernel sources, so a
-later change to the kernels invalidates it (the benchmark then reports
+per launch.  The result is stamped with a hash of the kernel's sources, so
+a later change to that kernel invalidates it (the benchmark then reports
 traffic as null).
 
     python -m paper_2110_07131_amd.profiling --fetch DIR1 --write DIR2 \\
@@ -26,14 +26,24 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 
 
-def source_hash() -> str:
-    """sha256 over the HIP sources and headers of the library (sorted names)."""
+# The sources a kernel is compiled from (its file and the headers it includes).
+KERNEL_SOURCES = {
+    "k_bfilter": ["batch_kernels.hip", "rk_batch.h", "rk_common.h", "rkmips.h"],
+    "k_bscan": ["batch_kernels.hip", "rk_batch.h", "rk_common.h", "rkmips.h"],
+    "k_filter": ["query_kernels.hip", "rk_kernels.h", "rk_common.h", "rkmips.h"],
+}
+
+
+def source_hash(kernel: str) -> str:
+    """sha256 over the sources of a kernel (csrc/ and include/)."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            with open(os.path.join(CSRC, f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_SOURCES[kernel]:
+        path = os.path.join(CSRC, f)
+        if not os.path.exists(path):
+            path = os.path.join(os.path.dirname(HERE), "include", f)
+        h.update(f.encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -101,7 +111,7 @@ def main():
     fk, nf = kernel_average(fr, a.kernel)
     wk, nw = kernel_average(wr, a.kernel)
     entry = {
-        "kernel": a.kernel, "key": a.key, "source_hash": source_hash(),
+        "kernel": a.kernel, "key": a.key, "source_hash": source_hash(a.kernel),
         "fetch_kib_per_launch": fk, "write_kib_per_launch": wk, "launches": [nf, nw],
         "copy_mb": a.copy_mb, "copy_fetch_kib": fmeas, "copy_write_kib": wmeas,
         "fetch_factor": ff, "write_factor": wf,
