@@ -189,3 +189,33 @@ def test_grouped_scan_many_flagged_pairs(nq):
     st = idx.stats()
     assert st["scan_long"] >= 64 * nq * 0.9
     idx.free()
+
+
+# --- limits: largest k_max, widest d ----------------------------------------
+
+@pytest.mark.parametrize("lb,prec", [(0, "fp32"), (130, "fp32"), (130, "bf16")])
+def test_batch_kmax_128(lb, prec):
+    # k_max = 128 (the limit): the scan's per-user lists exceed one wave
+    w = datagen.workload(700, 400, 20, 0.6, 40, seed=77)
+    rng = np.random.default_rng(77)
+    ks = rng.integers(1, 129, len(w.qidx)).astype(np.int32)
+    ks[:4] = 128
+    idx = Index.build(w.Q, w.P, 128, lb_items=lb, precision=prec)
+    off, ids = idx.reverse_kmips_batch(w.queries, ks)
+    check_csr(w.Q, w.P, w.queries, ks, off, ids)
+    idx.free()
+
+
+@pytest.mark.parametrize("d,lb", [(512, 0), (512, 16), (257, 0), (257, 16)])
+def test_batch_widest_dimensions(d, lb):
+    # d = 512 (the limit) and an odd d: tiles too wide for the batched filter
+    # go through the one-query path inside the batch call
+    w = datagen.workload(300, 150, d, 0.5, 12, seed=d)
+    rng = np.random.default_rng(d)
+    ks = rng.integers(1, 9, len(w.qidx)).astype(np.int32)
+    idx = Index.build(w.Q, w.P, 8, lb_items=lb)
+    off, ids = idx.reverse_kmips_batch(w.queries, ks)
+    check_csr(w.Q, w.P, w.queries, ks, off, ids)
+    for qi, k in zip(w.qidx[:4], ks[:4]):
+        assert np.array_equal(idx.reverse_kmips(w.P[qi], int(k)), oracle.brute(w.Q, w.P, w.P[qi], int(k)))
+    idx.free()
