@@ -14,6 +14,7 @@ HIP events in the same run, and the CPU oracle timed on the host cores.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -214,8 +215,12 @@ def serve_main(args):
         ntot = args.serve_warmup + args.serve_requests
         cat, qs, ks = draw(ntot)
         gaps = rng.exponential(1e3 / lam, ntot)
+        # the load generator must not pause (its lateness counts as latency)
+        gc.collect()
+        gc.disable()
         arrivals = srv.now_ms() + 1.0 + np.cumsum(gaps)
         lat, span = run(cat, qs, ks, arrivals)
+        gc.enable()
         m = slice(args.serve_warmup, ntot)
         L, C = lat[m], cat[m]
         per = {names[c]: {"p50_ms": float(np.percentile(L[C == c], 50)),
@@ -224,7 +229,8 @@ def serve_main(args):
         loads.append({"load": frac, "offered_qps": lam,
                       "achieved_qps": ntot / (span / 1e3),
                       "p50_ms": float(np.percentile(L, 50)), "p99_ms": float(np.percentile(L, 99)),
-                      "per_catalog": per})
+                      "per_catalog": per,
+                      "p99_ms_by_tenth": [float(np.percentile(x, 99)) for x in np.array_split(L, 10)]})
         print(f"[serve] load {frac}: offered {lam:.0f}/s, p50 {loads[-1]['p50_ms']:.3f} ms, "
               f"p99 {loads[-1]['p99_ms']:.3f} ms", file=sys.stderr, flush=True)
     line = {
