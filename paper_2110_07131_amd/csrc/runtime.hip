@@ -528,11 +528,16 @@ BatchSizes batch_sizes(const rk_index* h, int32_t chunk) {
   return z;
 }
 
-// Queries per chunk of the batched path for a batch of nq queries.
+// Queries per chunk of the batched path for a batch of nq queries.  With a
+// bounded table every survivor of the filter takes a pair slot; the chunk is
+// sized so that up to a quarter of all (user, query) pairs fit the slots (a
+// larger share would spill into the filter's in-kernel float64 fallback).
 int32_t batch_chunk(const rk_index* h, int64_t nq) {
   const int64_t W = bitmap_words(h->ix.n);
-  return (int32_t)std::max<int64_t>(
-      1, std::min<int64_t>({nq, (int64_t)kBatchChunkMax, kBitmapBudget / (W * 4)}));
+  int64_t c = std::min<int64_t>({nq, (int64_t)kBatchChunkMax, kBitmapBudget / (W * 4)});
+  if (!h->ix.exact && h->opts.pair_cap == 0)
+    c = std::min<int64_t>(c, std::max<int64_t>(TILE, kPairBudget / std::max<int64_t>(h->ix.n_pad / 4, 1)));
+  return (int32_t)std::max<int64_t>(1, c);
 }
 
 rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
