@@ -12,6 +12,7 @@
 // Algorithm 2 (bounded-table mode) or the float64 recheck.  Results are
 // per-query bitmaps over original user ids, turned into CSR rows at the end.
 #include "rk_batch.h"
+#include <climits>
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -582,10 +583,9 @@ __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView b
 // the users that have such pairs only, up to each user's largest limit, and
 // the flagged pairs are decided at the end.
 constexpr int kShortTiles = 4;
+constexpr int kUserPairs = 8;  // flagged pairs per user tracked for the early exit
 constexpr int kFlagCap = 1024;  // flagged pairs listed in LDS per block
 
-// List length per user: k_max + 2 rounded up to a multiple of 4.
-__host__ __device__ inline int bscan_list_len(int kmax) { return (kmax + 2 + 3) / 4 * 4; }
 
 template <int NV>
 __device__ __forceinline__ void load_item_tile(const DevIndex& ix, int64_t I, int t,
@@ -618,16 +618,9 @@ __device__ __forceinline__ float dot32_col(const float* __restrict__ q, const fl
   return acc;
 }
 
-__device__ __forceinline__ int norm_limit(const DevIndex& ix, float csu, float lo, int from) {
-  // first item i >= from with csu * |p_i| <= lo (items are norm-sorted)
-  int a = from, b = (int)ix.m;
-  while (a < b) {
-    const int mid = (a + b) >> 1;
-    if (csu * ix.normP[mid] <= lo) b = mid;
-    else a = mid + 1;
-  }
-  return a;
-}
+// Order-preserving map between the bits of a float and an int, its own
+// inverse: for non-NaN floats a < b iff fkey(bits a) < fkey(bits b).
+__device__ __forceinline__ int fkey(int b) { return b >= 0 ? b : b ^ 0x7fffffff; }
 
 // An undecided pair, decided exactly from the user's list of the k_max
 // largest products of the prefix (values and item ids): entries certainly
@@ -635,11 +628,16 @@ __device__ __forceinline__ int norm_limit(const DevIndex& ix, float csu, float l
 // (usually the one item equal to q), and the items outside the list are below
 // its last entry, certainly not above f(q,u) unless that entry is itself in
 // the band, when the float64 scan decides.  The prefix must reach the pair's
-// Corollary 1 limit.
+// Corollary 1 limit; when it does not (short_prefix), the float64 scan
+// decides directly.
 __device__ __forceinline__ bool resolve_pair(const DevIndex& ix, const BatchView& bv, int64_t u,
                                           int32_t jj, int k, float lo, float hi, float nu,
                                           const float* tk, const int32_t* ti, int K,
-                                          unsigned long long& full_scans) {
+                                          bool short_prefix, unsigned long long& full_scans) {
+  if (short_prefix) {
+    ++full_scans;
+    return decide_f64(ix, bv, u, jj);
+  }
   const float* urow = ix.Qrow + u * ix.d;
   const float* qrow = bv.qs + (int64_t)bv.perm[jj] * ix.d;
   double fq = 0.0;
@@ -667,6 +665,26 @@ __device__ __forceinline__ bool resolve_pair(const DevIndex& ix, const BatchView
   return decide_f64(ix, bv, u, jj);
 }
 
+// Four lanes of a quad exchange a value (lane ^ 1, lane ^ 2).
+__device__ __forceinline__ int quad_xor1(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ int quad_xor2(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false); }
+
+// (value, position) minimum over the four lanes of a quad; ties go to the
+// smaller position, so all four lanes agree.
+__device__ __forceinline__ void quad_min(float& v, int& p) {
+  float ov = __int_as_float(quad_xor1(__float_as_int(v)));
+  int op = quad_xor1(p);
+  if (ov < v || (ov == v && op < p)) v = ov, p = op;
+  ov = __int_as_float(quad_xor2(__float_as_int(v)));
+  op = quad_xor2(p);
+  if (ov < v || (ov == v && op < p)) v = ov, p = op;
+}
+
+__device__ __forceinline__ int quad_sum(int v) {
+  v += quad_xor1(v);
+  return v + quad_xor2(v);
+}
+
 template <int NV>
 __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   const int64_t B = blockIdx.x;
@@ -676,10 +694,13 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int half = lane >> 5, col = lane & 31;
   const int uh = wave & 1, ih = wave >> 1;
+  // list upkeep: the four lanes of quad uo serve user uo; lane sub holds the
+  // list entries j = 4i + sub
+  const int uo = t >> 2, sub = t & 3;
   // K >= k_max + 2 list entries (a multiple of 4): the entry after the k-th
   // is usually not the item equal to q, so an undecided pair rarely needs
   // the float64 scan
-  const int d = ix.d, d2 = d + (d & 1), K = bscan_list_len(ix.kmax);
+  const int d = ix.d, d2 = d + (d & 1), K = bscan_list_len(ix.kmax), K4 = K / 4;
   float* ubuf = (float*)lds_raw;        // [d2][64] users of the block
   float* pbuf = ubuf + d2 * TILE;       // [d2][64] current item tile
   float* cand = pbuf + d2 * TILE;       // [64][64] candidates of the tile per user
@@ -687,10 +708,22 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   int32_t* topi = (int32_t*)(topk + TILE * K);  // [64][K] their item ids (-1: none)
   float* thr = (float*)(topi + TILE * K);       // [64] smallest list value
   int* ccnt = (int*)(thr + TILE);       // [64] candidates per user
-  int* Tu = ccnt + TILE;                // [64] scan limit per user (long pass)
-  uint8_t* crow = (uint8_t*)(Tu + TILE);  // [64][64] candidate rows within the tile
-  __shared__ int nflag;
+  int* open = ccnt + TILE;              // [64] 1 while a flagged pair of the user needs items
+  int* Cov = open + TILE;               // [64] items covered by the user's list
+  uint8_t* crow = (uint8_t*)(Cov + TILE);  // [64][64] candidate rows within the tile
+  __shared__ int nflag, more_w[4];
   __shared__ int32_t flist[kFlagCap];  // slots of the flagged pairs
+  // Long pass, per user: kUserPairs slots of flagged pairs (largest k,
+  // smallest lower and largest upper bound of f(q,u), as ordered integer
+  // keys); the last slot holds the extremes over the user's remaining pairs,
+  // which settle when it does.  A slot settles once the list has k entries
+  // certainly above its upper bound (its pairs are no: Alg. 2's early exit)
+  // or the scan reaches its Corollary 1 limit (cs|u||p_i| <= its lower
+  // bound); a user stops when all its slots have.  Also the user's error
+  // bound of a product.
+  __shared__ int npu[TILE];
+  __shared__ int pk_s[TILE * kUserPairs], plo_s[TILE * kUserPairs], phi_s[TILE * kUserPairs];
+  __shared__ float eu[TILE];
   const int32_t* clist = bv.bchunks + B * bv.maxc;
 
   {
@@ -701,27 +734,67 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
       if (t < TILE) ubuf[d * TILE + t] = 0.f;
       else if (t < 2 * TILE) pbuf[d * TILE + t - TILE] = 0.f;
     }
+    // lists carried from the previous chunks of this call (or empty)
+    const int64_t g0 = B * TILE * (int64_t)K;
     for (int i = t; i < TILE * K; i += 256) {
-      topk[i] = -INFINITY;
-      topi[i] = -1;
+      const bool have = bv.carry_in && bv.gdone[B * TILE + i / K] > 0;
+      topk[i] = have ? bv.gl_v[g0 + i] : -INFINITY;
+      topi[i] = have ? bv.gl_i[g0 + i] : -1;
     }
     if (t < TILE) {
-      thr[t] = -INFINITY;
+      const int cv = bv.carry_in ? bv.gdone[B * TILE + t] : 0;
+      Cov[t] = cv;
+      thr[t] = cv > 0 ? bv.gl_v[g0 + (int64_t)t * K + K - 1] : -INFINITY;
       ccnt[t] = 0;
-      Tu[t] = 0;
+      open[t] = 0;
+      npu[t] = 0;
+    }
+    for (int i = t; i < TILE * kUserPairs; i += 256) {
+      pk_s[i] = 0;
+      plo_s[i] = INT_MAX;
+      phi_s[i] = INT_MIN;
     }
     if (t == 0) nflag = 0;
   }
   const int nshort = (int)min((int64_t)kShortTiles, (int64_t)ix.mB);
   unsigned long long c_scan = 0, c_l2 = 0, c_f64 = 0, c_long = 0, c_full = 0;
-  // list minimum of user t (t < 64) and its position, kept by thread t
-  float mn = -INFINITY;
-  int mp = 0;
+  // Quad uo: its lane's smallest entry (lmn at lmp) and the list's (gmn at
+  // gpos).  The lists are sorted (or empty) here and after every pass, the
+  // minimum last.
+  float lmn, gmn;
+  int lmp, gpos;
+  auto list_reset = [&]() {
+    lmp = K - 4 + sub;
+    lmn = topk[uo * K + lmp];
+    gpos = K - 1;
+    gmn = topk[uo * K + K - 1];
+  };
+  // Long pass, quad uo: its user's slots still open (bit p); per slot k,
+  // bounds and the number of list entries v with v - e > hi, kept as entries
+  // are replaced; hmin is the smallest upper bound of an open slot (a product
+  // below it changes no count).
+  unsigned rem = 0;
+  float eut = 0.f, csut = 0.f, hmin = INFINITY;
+  int pk[kUserPairs], cnt[kUserPairs];
+  float plo[kUserPairs], ph[kUserPairs];
+  // settles the slots decided no, or covered to their limit at item pos
+  // (npos = |p_pos|)
+  auto settle = [&](int pos, float npos) {
+    const bool end = pos >= ix.m;
+    float h = INFINITY;
+#pragma unroll
+    for (int p = 0; p < kUserPairs; ++p) {
+      if (cnt[p] >= pk[p] || end || csut * npos <= plo[p]) rem &= ~(1u << p);
+      if ((rem >> p) & 1u) h = fminf(h, ph[p]);
+    }
+    hmin = h;
+  };
 
-  // Item tiles [I0, I1): MFMA quarter (user half uh, item half ih) for the
-  // active users; products above the user's list minimum become candidates;
-  // thread u then puts each candidate in place of its list's minimum.  The
-  // next tile is prefetched into registers.
+  // Item tiles from I0 (to I1, or until no user of the block has an open
+  // pair): MFMA quarter (user half uh, item half ih) for the active users;
+  // products above the user's list minimum become candidates; the user's
+  // quad then puts each candidate in place of the list's minimum.  The next
+  // tile is prefetched into registers.
   u32x4 pf[NV];
   auto scan_tiles = [&](int I0, int I1, bool all_users) {
     if (I0 >= I1) return;
@@ -731,8 +804,12 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
     if (I0 + 1 < I1) load_item_tile(ix, I0 + 1, t, pf);
     for (int I = I0; I < I1; ++I) {
       __syncthreads();  // pbuf holds tile I; candidate lists are empty
+      if (!all_users && !(more_w[0] | more_w[1] | more_w[2] | more_w[3])) break;
+      const int64_t pos = (int64_t)(I + 1) * TILE;  // items covered after this tile
+      const float npos = !all_users && pos < ix.m ? ix.normP[pos] : 0.f;
       const int ul = uh * 32 + col;
-      const bool act = all_users || Tu[ul] > I * TILE;
+      // users whose list already covers the tile skip it
+      const bool act = (all_users || open[ul]) && I * TILE >= Cov[ul];
       if (__ballot(act)) {
         f32x16 acc = {}, acc2 = {};
         const float* pf_ = pbuf + ih * 32 + col + half * TILE;
@@ -773,48 +850,68 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
         store_item_tile(pbuf, d, t, pf);
         if (I + 2 < I1) load_item_tile(ix, I + 2, t, pf);
       }
-      if (t < TILE) {
-        const int c = ccnt[t];
-        if (c > 0) {
-          float* tk = topk + t * K;
-          int32_t* ti = topi + t * K;
-          for (int i = 0; i < c; ++i) {
-            const float v = cand[t * TILE + i];
-            if (v > mn) {
-              tk[mp] = v;
-              ti[mp] = I * TILE + crow[t * TILE + i];
-              mn = INFINITY;
-              const float4* t4 = (const float4*)tk;
-#pragma unroll 2
-              for (int p = 0; p < K / 4; ++p) {
-                const float4 x = t4[p];
-                if (x.x < mn) mn = x.x, mp = 4 * p;
-                if (x.y < mn) mn = x.y, mp = 4 * p + 1;
-                if (x.z < mn) mn = x.z, mp = 4 * p + 2;
-                if (x.w < mn) mn = x.w, mp = 4 * p + 3;
+      {
+        const bool was_act = (all_users || open[uo]) && I * TILE >= Cov[uo];
+        const int c = ccnt[uo];
+        float* tk = topk + uo * K;
+        int32_t* ti = topi + uo * K;
+        for (int i = 0; i < c; ++i) {
+          const float v = cand[uo * TILE + i];
+          if (v > gmn) {
+            if (!all_users && v - eut > hmin) {
+#pragma unroll
+              for (int p = 0; p < kUserPairs; ++p)
+                cnt[p] += (int)(v - eut > ph[p]) - (int)(gmn - eut > ph[p]);
+            }
+            if ((gpos & 3) == sub) {  // the lane holding the minimum replaces it
+              tk[gpos] = v;
+              ti[gpos] = I * TILE + crow[uo * TILE + i];
+              lmn = INFINITY;
+              for (int e = 0; e < K4; ++e) {
+                const float x = tk[4 * e + sub];
+                if (x < lmn) lmn = x, lmp = 4 * e + sub;
               }
             }
+            float a = lmn;
+            int pa = lmp;
+            quad_min(a, pa);
+            gmn = a;
+            gpos = pa;
           }
-          thr[t] = mn;
-          ccnt[t] = 0;
         }
-        if (bv.ctr && (all_users || Tu[t] > I * TILE)) {
-          const int64_t left = ix.m - (int64_t)I * TILE;
-          c_scan += (unsigned long long)(left < TILE ? left : TILE);
+        if (was_act && !all_users && rem) settle((int)pos, npos);
+        if (sub == 0) {
+          if (c > 0) {
+            thr[uo] = gmn;
+            ccnt[uo] = 0;
+          }
+          if (was_act) {
+            Cov[uo] = (int)pos;  // the list covers the items [0, (I+1)*64)
+            if (!all_users && !rem) open[uo] = 0;  // every pair settled: the user stops
+            if (bv.ctr) c_scan += (unsigned long long)min((int64_t)TILE, ix.m - (int64_t)I * TILE);
+          }
+        }
+        if (!all_users) {
+          const unsigned long long still = __ballot(rem != 0u);
+          if (lane == 0) more_w[wave] = still != 0ull;
         }
       }
     }
     __syncthreads();
-    // Sort every list in descending order (value, then item id).
+    // Sort every list in descending order (value, then item id); S lanes per
+    // list (S a power of two >= K), 64 / S lists per wave at once.
     if (K <= TILE) {
-      for (int uu = wave; uu < TILE; uu += 4) {
-        float v = lane < K ? topk[uu * K + lane] : -INFINITY;
-        int32_t id = lane < K ? topi[uu * K + lane] : INT32_MAX;
-        for (int size = 2; size <= TILE; size <<= 1) {
+      const int S = K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : K <= 32 ? 32 : 64;
+      const int per = TILE / S, g = lane / S, j = lane % S;
+      for (int u0 = wave * per; u0 < TILE; u0 += 4 * per) {
+        const int uu = u0 + g;
+        float v = j < K ? topk[uu * K + j] : -INFINITY;
+        int32_t id = j < K ? topi[uu * K + j] : INT32_MAX;
+        for (int size = 2; size <= S; size <<= 1) {
           for (int stride = size >> 1; stride > 0; stride >>= 1) {
             const float ov = __shfl_xor(v, stride);
             const int32_t oid = __shfl_xor(id, stride);
-            const bool keep_max = ((lane & stride) == 0) == ((lane & size) == 0);
+            const bool keep_max = ((j & stride) == 0) == ((j & size) == 0);
             const bool other_greater = ov > v || (ov == v && oid < id);
             const bool other_less = ov < v || (ov == v && oid > id);
             if (keep_max ? other_greater : other_less) {
@@ -823,9 +920,9 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
             }
           }
         }
-        if (lane < K) {
-          topk[uu * K + lane] = v;
-          topi[uu * K + lane] = id == INT32_MAX ? -1 : id;
+        if (j < K) {
+          topk[uu * K + j] = v;
+          topi[uu * K + j] = id == INT32_MAX ? -1 : id;
         }
       }
     } else if (t < TILE) {
@@ -845,14 +942,12 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
       }
     }
     __syncthreads();
-    if (t < TILE) {
-      mn = topk[t * K + K - 1];
-      mp = K - 1;
-    }
+    list_reset();
   };
 
+  __syncthreads();
+  list_reset();
   scan_tiles(0, nshort, true);
-  const int64_t S0 = (int64_t)nshort * TILE;  // items covered by the short pass
   const float e0 = ix.eps_rel32 * ix.normP[0];  // times |u|, plus eps_abs: any product's bound
 
   // f(q,u) in [lo, hi]: float32 bounds (recomputed from the float32 rows in
@@ -921,11 +1016,14 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
         } else if (lo >= csu * ix.normP[k - 1]) {
           cls = 1;  // Lemma 2
           ++c_l2;
-        } else if (S0 >= ix.m || csu * ix.normP[S0] <= lo) {
+        } else if (Cov[ul] >= ix.m || csu * ix.normP[Cov[ul]] <= lo) {
           cls = (kth + e <= lo) ? 1 : 3;
         } else {
           cls = 2;
-          atomicMax(&Tu[ul], norm_limit(ix, csu, lo, (int)S0));
+          const int at = ul * kUserPairs + min(atomicAdd(&npu[ul], 1), kUserPairs - 1);
+          atomicMax(&pk_s[at], k);
+          atomicMin(&plo_s[at], fkey(__float_as_int(lo)));
+          atomicMax(&phi_s[at], fkey(__float_as_int(hi)));
         }
       }
       bv.pair_st[slot[g]] = cls == 2;
@@ -936,7 +1034,8 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
       }
       bool yes = cls == 1;
       if (cls == 3) {
-        yes = resolve_pair(ix, bv, u, jj, k, lo, hi, nu, topk + ul * K, topi + ul * K, K, c_full);
+        yes = resolve_pair(ix, bv, u, jj, k, lo, hi, nu, topk + ul * K, topi + ul * K, K, false,
+                           c_full);
         ++c_f64;
       }
       if (yes) set_pair_result(bv, ix, u, bv.perm[jj]);
@@ -944,33 +1043,75 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   }
   __syncthreads();
 
-  // Long pass: flagged pairs, their users' scan continued to each user's limit.
+  // Long pass: flagged pairs, their users' scan continued until each of
+  // their pairs has settled.
   auto decide_flagged = [&](int64_t slot) {
     const int64_t u = bv.pair_u[slot];
     const int ul = (int)(u - B * TILE);
     const int32_t jj = bv.pair_j[slot];
     const int k = bv.k_s[jj];
     const float nu = ix.normQ[u];
-    const float e = e0 * nu + ix.eps_abs;
+    const float e = eu[ul];
     const float kth = topk[ul * K + k - 1];
     float lo, hi;
     pair_bounds(slot, ul, jj, nu, lo, hi);
+    const float csu = ix.cs_inflate * nu;
+    // the scan stopped before this pair's limit: not expected, as a user
+    // stops only when each of its pairs is decided no or covered to its
+    // limit; float64 then decides
+    const bool short_prefix = Cov[ul] < ix.m && csu * ix.normP[Cov[ul]] > lo;
     bool yes;
     if (kth - e > hi) {
       yes = false;
-    } else if (kth + e <= lo) {
+    } else if (!short_prefix && kth + e <= lo) {
       yes = true;
     } else {
-      yes = resolve_pair(ix, bv, u, jj, k, lo, hi, nu, topk + ul * K, topi + ul * K, K, c_full);
+      yes = resolve_pair(ix, bv, u, jj, k, lo, hi, nu, topk + ul * K, topi + ul * K, K,
+                         short_prefix, c_full);
       ++c_f64;
     }
     if (yes) set_pair_result(bv, ix, u, bv.perm[jj]);
   };
   const int nfl = nflag;
   if (nfl > 0) {
-    int tmax = 0;
-    for (int i = 0; i < TILE; ++i) tmax = max(tmax, Tu[i]);
-    scan_tiles(nshort, (int)((tmax + TILE - 1) / TILE), false);
+    {
+      const float nuo = ix.normQ[B * TILE + uo];
+      eut = e0 * nuo + ix.eps_abs;
+      csut = ix.cs_inflate * nuo;
+      if (t < TILE) eu[t] = e0 * ix.normQ[B * TILE + t] + ix.eps_abs;
+      const int np = npu[uo];
+#pragma unroll
+      for (int p = 0; p < kUserPairs; ++p) {
+        const bool have = p < np;
+        pk[p] = have ? pk_s[uo * kUserPairs + p] : INT_MAX;
+        plo[p] = have ? __int_as_float(fkey(plo_s[uo * kUserPairs + p])) : INFINITY;
+        ph[p] = have ? __int_as_float(fkey(phi_s[uo * kUserPairs + p])) : INFINITY;
+        rem |= (unsigned)have << p;
+        cnt[p] = 0;
+      }
+      if (rem) {
+        for (int i = 0; i < K4; ++i) {
+          const float a = topk[uo * K + 4 * i + sub] - eut;
+#pragma unroll
+          for (int p = 0; p < kUserPairs; ++p) cnt[p] += a > ph[p];
+        }
+#pragma unroll
+        for (int p = 0; p < kUserPairs; ++p) cnt[p] = quad_sum(cnt[p]);
+        // users whose lists already settle every flagged pair stop here
+        const int cv = Cov[uo];
+        settle(cv, cv < ix.m ? ix.normP[cv] : 0.f);
+      }
+      if (sub == 0) open[uo] = rem != 0u;
+      const unsigned long long still = __ballot(rem != 0u);
+      if (lane == 0) more_w[wave] = still != 0ull;
+    }
+    __syncthreads();
+    // tiles from the smallest coverage of a user with an open pair
+    int tmin = INT_MAX;
+    for (int i = 0; i < TILE; ++i)
+      if (open[i]) tmin = min(tmin, Cov[i]);
+    if (tmin < INT_MAX) scan_tiles(tmin / TILE, (int)ix.mB, false);
+    __syncthreads();
     if (nfl <= kFlagCap) {
       for (int i = t; i < nfl; i += 256) decide_flagged(flist[i]);
     } else {  // more than the list holds: find them by their flags
@@ -981,6 +1122,17 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
         if (bv.pair_st[slot]) decide_flagged(slot);
       }
     }
+  }
+
+  // the lists (sorted) and what they cover, for the call's next chunks
+  if (bv.carry_out) {
+    __syncthreads();
+    const int64_t g0 = B * TILE * (int64_t)K;
+    for (int i = t; i < TILE * K; i += 256) {
+      bv.gl_v[g0 + i] = topk[i];
+      bv.gl_i[g0 + i] = topi[i];
+    }
+    if (t < TILE) bv.gdone[B * TILE + t] = Cov[t];
   }
 
   if (bv.ctr) {
@@ -1092,6 +1244,19 @@ __global__ void __launch_bounds__(256) k_bassemble(BatchView bv, int32_t nq,
   }
 }
 
+// Bounded table: the carried per-user scan state starts empty for a call.
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+void launch_bscan_reset(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
+  if (ix.exact || ix.n_pad == 0) return;
+  const int64_t blocks = std::min<int64_t>((ix.n_pad + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, bv.gdone, ix.n_pad, 0);
+}
+
 // Bounded table: empty chunk lists before the filter.
 __global__ void k_bclear(int32_t* __restrict__ bcnt, int32_t nB, int32_t* __restrict__ nchunks) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1151,8 +1316,14 @@ void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
 
 size_t bscan_lds_bytes(const DevIndex& ix) {
   const size_t d2 = (size_t)(ix.d + (ix.d & 1));
-  return (2 * d2 * TILE + TILE * TILE + 2 * (size_t)TILE * bscan_list_len(ix.kmax) + 3 * TILE) * 4 +
+  return (2 * d2 * TILE + TILE * TILE + 2 * (size_t)TILE * bscan_list_len(ix.kmax) + 4 * TILE) * 4 +
          TILE * TILE;
+}
+
+size_t bscan_static_lds() {
+  hipFuncAttributes a{};
+  if (hipFuncGetAttributes(&a, (const void*)k_bscan<2>) != hipSuccess) return 16384;
+  return a.sharedSizeBytes;
 }
 
 template <int NV>

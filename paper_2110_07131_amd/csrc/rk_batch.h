@@ -7,6 +7,9 @@ namespace rk {
 constexpr int kBatchChunkMax = 4096;  // queries per chunk (single-workgroup sort in LDS)
 constexpr int kPairChunk = 256;       // slots per pair chunk (bounded table)
 
+// Scan list length per user: k_max + 2 rounded up to a multiple of 4.
+__host__ __device__ inline int bscan_list_len(int kmax) { return (kmax + 2 + 3) / 4 * 4; }
+
 struct BatchView {
   const float* qs;              // chunk queries [nq][d], caller order
   float* qn;                    // [nq] |q| rounded up, caller order
@@ -35,6 +38,14 @@ struct BatchView {
   int32_t maxc;                 // list capacity per block
   int32_t* bcnt;                // [nB] chunks of the filter's pairs per block
   int32_t* bchunks;             // [nB][maxc] their ids
+  // Per-user scan state carried across the chunks of one batch call: the
+  // largest approximate products of the items [0, gdone[u]) (descending,
+  // with item ids), bscan_list_len(k_max) entries per user.
+  float* gl_v;
+  int32_t* gl_i;
+  int32_t* gdone;               // [n_pad] items covered (a multiple of 64); 0 at a call's start
+  int32_t carry_in;             // 1: the lists hold the previous chunks' state
+  int32_t carry_out;            // 1: later chunks follow (store the lists)
   unsigned long long* ctr;      // statistics or nullptr
 };
 
@@ -46,6 +57,9 @@ void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 // Dynamic LDS of the grouped linear scan (bounded table).
 size_t bscan_lds_bytes(const DevIndex& ix);
+size_t bscan_static_lds();  // its static LDS (the same for every instantiation)
+// Bounded table: the carried scan state starts empty for a batch call.
+void launch_bscan_reset(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 // offs[0] must hold the chunk's first offset; writes offs[1..nq] and ids.
 void launch_bassemble(const BatchView& bv, int32_t nq, const int64_t* base, int64_t* offs,
                       int32_t* ids, int64_t cap, hipStream_t s);

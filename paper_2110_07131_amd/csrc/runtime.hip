@@ -104,7 +104,8 @@ struct rk_index {
             *pair_j = nullptr, *ks_dev = nullptr;
     // bounded table: chunked pair slots, per-block chunk lists
     int32_t *pair_st = nullptr, *cfill = nullptr, *nchunks = nullptr, *bcnt = nullptr,
-            *bchunks = nullptr;
+            *bchunks = nullptr, *gl_i = nullptr, *gdone = nullptr;
+    float* gl_v = nullptr;
     int32_t chunk_cap = 0, maxc = 0;
     uint32_t* bits = nullptr;
     unsigned long long* counts = nullptr;
@@ -523,7 +524,8 @@ BatchSizes batch_sizes(const rk_index* h, int32_t chunk) {
               chunk * W * 4 + chunk * 8 + chunk + 4 + pc * 12 + chunk * 4;
   if (!ix.exact)
     b += std::max<int64_t>(pc, 1) * 4 + std::max<int64_t>(z.chunk_cap, 1) * 4 + 4 +
-         std::max<int64_t>(ix.nB, 1) * 4 * (1 + z.maxc);
+         std::max<int64_t>(ix.nB, 1) * 4 * (1 + z.maxc) +
+         std::max<int64_t>(ix.n_pad, 1) * (8 * (int64_t)bscan_list_len(ix.kmax) + 4);
   z.bytes = b;
   return z;
 }
@@ -548,9 +550,10 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
                   (void*)b.perm, (void*)b.k_s, (void*)b.npairs, (void*)b.pair_u, (void*)b.pair_j,
                   (void*)b.ks_dev, (void*)b.bits, (void*)b.counts, (void*)b.all,
                   (void*)b.pair_st, (void*)b.cfill, (void*)b.nchunks, (void*)b.bcnt,
-                  (void*)b.bchunks})
+                  (void*)b.bchunks, (void*)b.gl_v, (void*)b.gl_i, (void*)b.gdone})
     if (p) h->dfree(p);
-  b.pair_st = b.cfill = b.nchunks = b.bcnt = b.bchunks = nullptr;
+  b.pair_st = b.cfill = b.nchunks = b.bcnt = b.bchunks = b.gl_i = b.gdone = nullptr;
+  b.gl_v = nullptr;
   const DevIndex& ix = h->ix;
   const BatchSizes z = batch_sizes(h, chunk);
   const int64_t cp = round_up(chunk, TILE), W = bitmap_words(ix.n);
@@ -578,6 +581,10 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
     HIPTRY(h->dalloc(&b.nchunks, 1));
     HIPTRY(h->dalloc(&b.bcnt, std::max<int64_t>(ix.nB, 1)));
     HIPTRY(h->dalloc(&b.bchunks, (int64_t)std::max<int64_t>(ix.nB, 1) * b.maxc));
+    const int64_t nl = std::max<int64_t>(ix.n_pad, 1) * bscan_list_len(ix.kmax);
+    HIPTRY(h->dalloc(&b.gl_v, nl));
+    HIPTRY(h->dalloc(&b.gl_i, nl));
+    HIPTRY(h->dalloc(&b.gdone, std::max<int64_t>(ix.n_pad, 1)));
   }
   HIPTRY(hipMemsetAsync(b.bits, 0, (size_t)chunk * std::max<int64_t>(W, 1) * 4, h->stream));
   HIPTRY(hipMemsetAsync(b.counts, 0, (size_t)chunk * 8, h->stream));
@@ -618,7 +625,7 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
   if (nq == 0) return RK_OK;
   const size_t tile_bytes = ix.bf16 ? (size_t)ix.d16 * TILE * 2 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
   if (bfilter_lds_bytes(ix) > kMaxLds || tile_bytes > bfilter_max_tile_bytes() ||
-      (!ix.exact && bscan_lds_bytes(ix) + 8192 > kMaxLds)) {  // + static LDS of the scan
+      (!ix.exact && bscan_lds_bytes(ix) + bscan_static_lds() > kMaxLds)) {
     // too wide for the block-resident batched filter: one query at a time
     for (int64_t i = 0; i < nq; ++i) {
       rk_status st = enqueue_query(h, qs_dev + i * ix.d, ks[i], ids, cap, offs + i, offs + i + 1,
@@ -644,6 +651,10 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
     bv.pair_u = b.pair_u; bv.pair_j = b.pair_j; bv.pair_s = b.pair_s;
     bv.pair_st = b.pair_st; bv.cfill = b.cfill; bv.nchunks = b.nchunks;
     bv.chunk_cap = b.chunk_cap; bv.maxc = b.maxc; bv.bcnt = b.bcnt; bv.bchunks = b.bchunks;
+    bv.gl_v = b.gl_v; bv.gl_i = b.gl_i; bv.gdone = b.gdone;
+    bv.carry_in = c0 > 0;
+    bv.carry_out = c0 + nc < nq;
+    if (c0 == 0 && bv.carry_out) launch_bscan_reset(ix, bv, s);  // the scan state is per call
     bv.ctr = h->counting ? h->ctr_dev : nullptr;
     { Timer t(h, s, K_BPREP); launch_bprep(ix, bv, b.ks_dev, nc, s); }
     { Timer t(h, s, K_BFILTER); launch_bfilter(ix, bv, s); }

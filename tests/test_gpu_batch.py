@@ -191,6 +191,63 @@ def test_grouped_scan_many_flagged_pairs(nq):
     idx.free()
 
 
+def test_grouped_scan_lists_carried_across_chunks():
+    # 4,400 queries (two query chunks) over a catalog far longer than the
+    # short pass: the second chunk starts from the first chunk's per-user
+    # lists and scanned lengths
+    w = datagen.workload(400, 3000, 12, 0.7, 3000, seed=14)
+    rng = np.random.default_rng(14)
+    pick = rng.integers(0, 3000, 4400)
+    qs = np.ascontiguousarray(w.P[pick])
+    ks = rng.integers(1, 9, len(qs)).astype(np.int32)
+    idx = Index.build(w.Q, w.P, 8, lb_items=10)
+    idx.set_counting(True)
+    off, ids = idx.reverse_kmips_batch(qs, ks)
+    st = idx.stats()
+    assert st["scan_long"] > 0
+    for i in list(range(0, 4400, 23)) + [4095, 4096, 4399]:
+        assert np.array_equal(ids[off[i]:off[i + 1]], oracle.brute(w.Q, w.P, qs[i], int(ks[i]))), i
+    # the same queries one chunk at a time give the same rows
+    off2, ids2 = idx.reverse_kmips_batch(qs[4096:], ks[4096:])
+    assert np.array_equal(off2, off[4096:] - off[4096])
+    assert np.array_equal(ids2, ids[off[4096]:])
+    idx.free()
+
+
+def early_exit_case(rng):
+    # Users along +x.  The 300 largest items point along -x (never above q,
+    # but their norms put every limit past the short pass); the next 1,500
+    # are large and random, so the flagged pairs of the small queries meet k
+    # items above q within the first tiles of the long pass and stop there;
+    # the large queries are members for most users, settled before the long
+    # pass.
+    d = 6
+    Q = np.column_stack([1 + 0.2 * rng.random(128), 0.3 * rng.standard_normal((128, d - 1))])
+    away = np.column_stack([-5 - rng.random(300), 0.2 * rng.standard_normal((300, d - 1))])
+    mid = rng.standard_normal((1500, d))
+    mid *= (3 + rng.random((1500, 1))) / np.linalg.norm(mid, axis=1, keepdims=True)
+    small = 0.5 * rng.standard_normal((30, d))
+    P = np.vstack([away, mid, small]).astype(np.float32)
+    qs = np.column_stack([np.r_[0.5 + 0.3 * rng.random(40), 6.5 + 0.5 * rng.random(8)],
+                          0.2 * rng.standard_normal((48, d - 1))]).astype(np.float32)
+    ks = rng.integers(1, 7, len(qs)).astype(np.int32)
+    return Q.astype(np.float32), P, qs, ks
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_grouped_scan_early_exit(prec):
+    Q, P, qs, ks = early_exit_case(np.random.default_rng(60))
+    idx = Index.build(Q, P, 6, lb_items=8, precision=prec)
+    idx.set_counting(True)
+    off, ids = idx.reverse_kmips_batch(qs, ks)
+    check_csr(Q, P, qs, ks, off, ids)
+    st = idx.stats()
+    assert st["scan_long"] > 0
+    # without the early exit every flagged user would scan nearly all of P
+    assert st["scan_items"] < 0.4 * len(Q) * len(P)
+    idx.free()
+
+
 # --- limits: largest k_max, widest d ----------------------------------------
 
 @pytest.mark.parametrize("lb,prec", [(0, "fp32"), (130, "fp32"), (130, "bf16")])
