@@ -810,7 +810,65 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
       const int ul = uh * 32 + col;
       // users whose list already covers the tile skip it
       const bool act = (all_users || open[ul]) && I * TILE >= Cov[ul];
-      if (__ballot(act)) {
+      // Long pass with at most 8 active users (the block's last ones): wave w
+      // computes the products of the w-th and (w+4)-th active user over the
+      // tile on the vector ALU, one item per lane, instead of MFMA quarters.
+      unsigned long long am = 0;
+      if (!all_users) am = __ballot(open[lane] && I * TILE >= Cov[lane]);
+      if (!all_users && __popcll(am) <= 8) {
+        unsigned long long mk = am;
+        for (int i = 0; i < wave; ++i) mk &= mk - 1;
+        const int u0 = mk ? __ffsll(mk) - 1 : -1;
+        for (int i = 0; i < 4 && mk; ++i) mk &= mk - 1;
+        const int u1 = mk ? __ffsll(mk) - 1 : -1;
+        const int64_t left = ix.m - (int64_t)I * TILE;
+        const float* pc = pbuf + lane;
+        if (u0 >= 0 && u1 < 0) {
+          float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+          const float* x0 = ubuf + u0;
+          int k = 0;
+          for (; k + 4 <= d; k += 4) {
+            a0 = fmaf(pc[k * TILE], x0[k * TILE], a0);
+            a1 = fmaf(pc[(k + 1) * TILE], x0[(k + 1) * TILE], a1);
+            a2 = fmaf(pc[(k + 2) * TILE], x0[(k + 2) * TILE], a2);
+            a3 = fmaf(pc[(k + 3) * TILE], x0[(k + 3) * TILE], a3);
+          }
+          for (; k < d; ++k) a0 = fmaf(pc[k * TILE], x0[k * TILE], a0);
+          const float v = (a0 + a1) + (a2 + a3);
+          if (lane < left && v > thr[u0]) {
+            const int at = atomicAdd(&ccnt[u0], 1);
+            cand[u0 * TILE + at] = v;
+            crow[u0 * TILE + at] = (uint8_t)lane;
+          }
+        } else if (u1 >= 0) {
+          float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
+          const float* x0 = ubuf + u0;
+          const float* x1 = ubuf + u1;
+          int k = 0;
+          for (; k + 2 <= d; k += 2) {
+            const float p0 = pc[k * TILE], p1 = pc[(k + 1) * TILE];
+            a0 = fmaf(p0, x0[k * TILE], a0);
+            b0 = fmaf(p0, x1[k * TILE], b0);
+            a1 = fmaf(p1, x0[(k + 1) * TILE], a1);
+            b1 = fmaf(p1, x1[(k + 1) * TILE], b1);
+          }
+          if (k < d) {
+            a0 = fmaf(pc[k * TILE], x0[k * TILE], a0);
+            b0 = fmaf(pc[k * TILE], x1[k * TILE], b0);
+          }
+          const float va = a0 + a1, vb = b0 + b1;
+          if (lane < left && va > thr[u0]) {
+            const int at = atomicAdd(&ccnt[u0], 1);
+            cand[u0 * TILE + at] = va;
+            crow[u0 * TILE + at] = (uint8_t)lane;
+          }
+          if (lane < left && vb > thr[u1]) {
+            const int at = atomicAdd(&ccnt[u1], 1);
+            cand[u1 * TILE + at] = vb;
+            crow[u1 * TILE + at] = (uint8_t)lane;
+          }
+        }
+      } else if (__ballot(act)) {
         f32x16 acc = {}, acc2 = {};
         const float* pf_ = pbuf + ih * 32 + col + half * TILE;
         const float* uf = ubuf + uh * 32 + col + half * TILE;
