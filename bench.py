@@ -376,7 +376,7 @@ def main():
         "counters_per_step": {k: st[k] for k in ("blocks_visited", "blocks_pruned", "users_evaluated",
                                                  "lemma1_no", "lemma2_yes", "table_yes", "survivors",
                                                  "scan_items", "rechecks", "results", "scan_long",
-                                                 "scan_full_f64")},
+                                                 "scan_full_f64", "scan_handoff")},
         "build_ms": st0["build_ms"], "index_bytes": st0["footprint_bytes"],
         "cpu_baseline": cpu,
     }

@@ -106,7 +106,9 @@ typedef struct {
     int64_t scan_long;         /* batched scan: pairs whose Corollary 1 limit lies
                                   beyond the short pass (decided by the long pass) */
     int64_t scan_full_f64;     /* pairs decided by the full float64 scan */
-    int64_t reserved[6];
+    int64_t scan_handoff;      /* batched scan: users handed from their block (or
+                                  group) to a group pass of users from several blocks */
+    int64_t reserved[5];
 } rk_stats;
 
 /* Index fields readable with rk_index_export (sorted = descending norm). */

@@ -583,8 +583,13 @@ __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView b
 // the users that have such pairs only, up to each user's largest limit, and
 // the flagged pairs are decided at the end.
 constexpr int kShortTiles = 4;
-constexpr int kUserPairs = 8;  // flagged pairs per user tracked for the early exit
 constexpr int kFlagCap = 1024;  // flagged pairs listed in LDS per block
+constexpr int kHandoff = 8;     // at most this many users of a block still scanning: hand them over
+constexpr int kGroupHandoff = 16;  // the same for a group pass (but the last)
+constexpr int kGroupLevels = 2;    // group passes
+// ... and only with more than this many item tiles left (shorter tails cost
+// less where they are than the extra passes)
+constexpr int kHandoffMinTiles = 512;
 
 
 template <int NV>
@@ -685,11 +690,27 @@ __device__ __forceinline__ int quad_sum(int v) {
   return v + quad_xor2(v);
 }
 
-template <int NV>
+// GROUP = false: workgroup B = user block B, all passes; users still scanning
+// when at most kHandoff of the block are, are handed over.  GROUP = true:
+// workgroup B = the handed-over users 64B .. 64B+63 of the current list
+// (from any blocks), the long pass only, continued from their lists; it
+// hands over its last kGroupHandoff users in turn, but in the last group
+// pass.  Their pairs are decided by k_bdecide.
+template <int NV, bool GROUP>
 __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   const int64_t B = blockIdx.x;
-  const int nch = min(bv.bcnt[B], bv.maxc);
-  if (nch == 0) return;
+  int nch = 0, nusers = TILE;
+  const int32_t* glist = bv.sg_users + (int64_t)(bv.sg_level & 1) * ix.n_pad;  // group's input
+  int32_t* hlist = bv.sg_users + (int64_t)(GROUP ? (bv.sg_level & 1) ^ 1 : 0) * ix.n_pad;  // handed over
+  int32_t* hcount = bv.sg_count + (GROUP ? (bv.sg_level & 1) ^ 1 : 0);
+  if (GROUP) {
+    const int cnt = bv.sg_count[bv.sg_level & 1];
+    if (B * TILE >= cnt) return;
+    nusers = (int)min((int64_t)TILE, cnt - B * TILE);
+  } else {
+    nch = min(bv.bcnt[B], bv.maxc);
+    if (nch == 0) return;
+  }
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int half = lane >> 5, col = lane & 31;
@@ -725,26 +746,35 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   __shared__ int pk_s[TILE * kUserPairs], plo_s[TILE * kUserPairs], phi_s[TILE * kUserPairs];
   __shared__ float eu[TILE];
   const int32_t* clist = bv.bchunks + B * bv.maxc;
+  // sorted index of the user of column c (c < nusers)
+  auto urow = [&](int c) -> int64_t { return GROUP ? (int64_t)glist[B * TILE + c] : B * TILE + c; };
 
   {
-    const u32x4* src = (const u32x4*)(ix.Qt + B * (int64_t)d * TILE);
-    u32x4* dst = (u32x4*)ubuf;
-    for (int i = t; i < d * TILE / 4; i += 256) dst[i] = src[i];
+    if (GROUP) {  // gather the users' rows into columns
+      for (int i = t; i < d * TILE; i += 256) {
+        const int c = i & (TILE - 1);
+        ubuf[i] = c < nusers ? ix.Qrow[urow(c) * d + (i >> 6)] : 0.f;
+      }
+    } else {
+      const u32x4* src = (const u32x4*)(ix.Qt + B * (int64_t)d * TILE);
+      u32x4* dst = (u32x4*)ubuf;
+      for (int i = t; i < d * TILE / 4; i += 256) dst[i] = src[i];
+    }
     if (d & 1) {
       if (t < TILE) ubuf[d * TILE + t] = 0.f;
       else if (t < 2 * TILE) pbuf[d * TILE + t - TILE] = 0.f;
     }
-    // lists carried from the previous chunks of this call (or empty)
-    const int64_t g0 = B * TILE * (int64_t)K;
+    // lists carried from the previous chunks of this call or handed over (or empty)
     for (int i = t; i < TILE * K; i += 256) {
-      const bool have = bv.carry_in && bv.gdone[B * TILE + i / K] > 0;
-      topk[i] = have ? bv.gl_v[g0 + i] : -INFINITY;
-      topi[i] = have ? bv.gl_i[g0 + i] : -1;
+      const int c = i / K;
+      const bool have = GROUP ? c < nusers : bv.carry_in && bv.gdone[B * TILE + c] > 0;
+      const int64_t at = have ? urow(c) * K + (i - c * K) : 0;
+      topk[i] = have ? bv.gl_v[at] : -INFINITY;
+      topi[i] = have ? bv.gl_i[at] : -1;
     }
     if (t < TILE) {
-      const int cv = bv.carry_in ? bv.gdone[B * TILE + t] : 0;
-      Cov[t] = cv;
-      thr[t] = cv > 0 ? bv.gl_v[g0 + (int64_t)t * K + K - 1] : -INFINITY;
+      // padding columns of a group count as fully scanned
+      Cov[t] = GROUP ? (t < nusers ? bv.gdone[urow(t)] : (int)ix.m) : bv.carry_in ? bv.gdone[B * TILE + t] : 0;
       ccnt[t] = 0;
       open[t] = 0;
       npu[t] = 0;
@@ -769,6 +799,8 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
     gpos = K - 1;
     gmn = topk[uo * K + K - 1];
   };
+  bool handoff = false;  // the last users handed over to a group pass
+  int nopen0 = TILE;     // users still scanning when the long pass starts
   // Long pass, quad uo: its user's slots still open (bit p); per slot k,
   // bounds and the number of list entries v with v - e > hi, kept as entries
   // are replaced; hmin is the smallest upper bound of an open slot (a product
@@ -805,6 +837,13 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
     for (int I = I0; I < I1; ++I) {
       __syncthreads();  // pbuf holds tile I; candidate lists are empty
       if (!all_users && !(more_w[0] | more_w[1] | more_w[2] | more_w[3])) break;
+      // (a group hands over only if it started with more than twice as many)
+      if (!all_users && (!GROUP || (!bv.sg_last && nopen0 > 2 * kGroupHandoff)) &&
+          ix.mB - I > kHandoffMinTiles &&
+          __popcll(__ballot(open[lane] != 0)) <= (GROUP ? kGroupHandoff : kHandoff)) {
+        handoff = true;
+        break;
+      }
       const int64_t pos = (int64_t)(I + 1) * TILE;  // items covered after this tile
       const float npos = !all_users && pos < ix.m ? ix.normP[pos] : 0.f;
       const int ul = uh * 32 + col;
@@ -1005,8 +1044,9 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
 
   __syncthreads();
   list_reset();
-  scan_tiles(0, nshort, true);
+  if (sub == 0) thr[uo] = gmn;  // read after the next barrier
   const float e0 = ix.eps_rel32 * ix.normP[0];  // times |u|, plus eps_abs: any product's bound
+  if (!GROUP) scan_tiles(0, nshort, true);
 
   // f(q,u) in [lo, hi]: float32 bounds (recomputed from the float32 rows in
   // bf16 mode, where the filter's product is a bf16 one).
@@ -1021,7 +1061,7 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   // Pass 1: every pair, four chunks at a time (independent loads).
   // Classes: 0 no, 1 yes, 2 long (flagged), 3 resolve.
   constexpr int PG = 4;
-  for (int cg = 0; cg < nch; cg += PG) {
+  for (int cg = 0; cg < (GROUP ? 0 : nch); cg += PG) {
     int64_t slot[PG];
     bool ok[PG];
 #pragma unroll
@@ -1106,6 +1146,10 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   auto decide_flagged = [&](int64_t slot) {
     const int64_t u = bv.pair_u[slot];
     const int ul = (int)(u - B * TILE);
+    if (open[ul] == 2) {  // handed over: k_bdecide decides it
+      bv.pair_st[slot] = 2;
+      return;
+    }
     const int32_t jj = bv.pair_j[slot];
     const int k = bv.k_s[jj];
     const float nu = ix.normQ[u];
@@ -1130,20 +1174,28 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
     }
     if (yes) set_pair_result(bv, ix, u, bv.perm[jj]);
   };
-  const int nfl = nflag;
+  const int nfl = GROUP ? 1 : nflag;
   if (nfl > 0) {
     {
-      const float nuo = ix.normQ[B * TILE + uo];
+      const bool real = !GROUP || uo < nusers;
+      const float nuo = real ? ix.normQ[urow(uo)] : 0.f;
       eut = e0 * nuo + ix.eps_abs;
       csut = ix.cs_inflate * nuo;
-      if (t < TILE) eu[t] = e0 * ix.normQ[B * TILE + t] + ix.eps_abs;
-      const int np = npu[uo];
+      if (!GROUP && t < TILE) eu[t] = e0 * ix.normQ[B * TILE + t] + ix.eps_abs;
+      const int np = !real ? 0 : GROUP ? bv.st_np[urow(uo)] : npu[uo];
+      const int64_t so = real ? urow(uo) * kUserPairs : 0;
 #pragma unroll
       for (int p = 0; p < kUserPairs; ++p) {
         const bool have = p < np;
-        pk[p] = have ? pk_s[uo * kUserPairs + p] : INT_MAX;
-        plo[p] = have ? __int_as_float(fkey(plo_s[uo * kUserPairs + p])) : INFINITY;
-        ph[p] = have ? __int_as_float(fkey(phi_s[uo * kUserPairs + p])) : INFINITY;
+        if (GROUP) {
+          pk[p] = have ? bv.st_pk[so + p] : INT_MAX;
+          plo[p] = have ? bv.st_plo[so + p] : INFINITY;
+          ph[p] = have ? bv.st_ph[so + p] : INFINITY;
+        } else {
+          pk[p] = have ? pk_s[uo * kUserPairs + p] : INT_MAX;
+          plo[p] = have ? __int_as_float(fkey(plo_s[uo * kUserPairs + p])) : INFINITY;
+          ph[p] = have ? __int_as_float(fkey(phi_s[uo * kUserPairs + p])) : INFINITY;
+        }
         rem |= (unsigned)have << p;
         cnt[p] = 0;
       }
@@ -1165,12 +1217,47 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
     }
     __syncthreads();
     // tiles from the smallest coverage of a user with an open pair
-    int tmin = INT_MAX;
+    int tmin = INT_MAX, nopen = 0;
     for (int i = 0; i < TILE; ++i)
-      if (open[i]) tmin = min(tmin, Cov[i]);
-    if (tmin < INT_MAX) scan_tiles(tmin / TILE, (int)ix.mB, false);
+      if (open[i]) tmin = min(tmin, Cov[i]), ++nopen;
+    nopen0 = nopen;
+    if (!GROUP && nopen <= kHandoff && ix.mB - tmin / TILE > kHandoffMinTiles) handoff = nopen > 0;
+    else if (tmin < INT_MAX) scan_tiles(tmin / TILE, (int)ix.mB, false);
+    if (handoff) {
+      // users still scanning: a place in the next group pass, and from a
+      // block their pair slots (their sorted lists and coverage are stored
+      // below)
+      if (sub == 0 && open[uo]) {
+        const int64_t u = urow(uo);
+        hlist[atomicAdd(hcount, 1)] = (int32_t)u;
+        if (bv.ctr) atomicAdd(&bv.ctr[C_HANDOFF], 1ull);
+        if (!GROUP) {
+          const int np = min(npu[uo], kUserPairs);
+          bv.st_np[u] = np;
+          for (int p = 0; p < kUserPairs; ++p) {
+            if (p < np) {
+              bv.st_pk[u * kUserPairs + p] = pk[p];
+              bv.st_plo[u * kUserPairs + p] = plo[p];
+              bv.st_ph[u * kUserPairs + p] = ph[p];
+            }
+          }
+          open[uo] = 2;
+        }
+      }
+      if (!GROUP && t == 0) bv.sg_block[B] = 1;
+    }
     __syncthreads();
-    if (nfl <= kFlagCap) {
+    if (GROUP) {
+      // the lists (sorted), their coverage
+      for (int i = t; i < TILE * K; i += 256) {
+        const int c = i / K;
+        if (c < nusers) {
+          bv.gl_v[urow(c) * K + (i - c * K)] = topk[i];
+          bv.gl_i[urow(c) * K + (i - c * K)] = topi[i];
+        }
+      }
+      if (t < nusers) bv.gdone[urow(t)] = Cov[t];
+    } else if (nfl <= kFlagCap) {
       for (int i = t; i < nfl; i += 256) decide_flagged(flist[i]);
     } else {  // more than the list holds: find them by their flags
       for (int ci = 0; ci < nch; ++ci) {
@@ -1182,15 +1269,18 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
     }
   }
 
-  // the lists (sorted) and what they cover, for the call's next chunks
-  if (bv.carry_out) {
+  // the lists (sorted) and what they cover, for the call's next chunks and
+  // the users handed over
+  if (!GROUP && (bv.carry_out || handoff)) {
     __syncthreads();
     const int64_t g0 = B * TILE * (int64_t)K;
     for (int i = t; i < TILE * K; i += 256) {
-      bv.gl_v[g0 + i] = topk[i];
-      bv.gl_i[g0 + i] = topi[i];
+      if (bv.carry_out || open[i / K] == 2) {
+        bv.gl_v[g0 + i] = topk[i];
+        bv.gl_i[g0 + i] = topi[i];
+      }
     }
-    if (t < TILE) bv.gdone[B * TILE + t] = Cov[t];
+    if (t < TILE && (bv.carry_out || open[t] == 2)) bv.gdone[B * TILE + t] = Cov[t];
   }
 
   if (bv.ctr) {
@@ -1207,6 +1297,61 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
       if (c_l2) atomicAdd(&bv.ctr[C_L2YES], c_l2);
       if (c_f64) atomicAdd(&bv.ctr[C_RCHK], c_f64);
       if (c_scan) atomicAdd(&bv.ctr[C_SCAN], c_scan);
+    }
+  }
+}
+
+// The flagged pairs of the users a block handed over, decided from their
+// final lists (global), as in the block's own long pass.
+__global__ void __launch_bounds__(256) k_bdecide(DevIndex ix, BatchView bv) {
+  const int64_t B = blockIdx.x;
+  if (!bv.sg_block[B]) return;
+  const int t = threadIdx.x, lane = t & 63;
+  const int nch = min(bv.bcnt[B], bv.maxc);
+  const int K = bscan_list_len(ix.kmax);
+  const float e0 = ix.eps_rel32 * ix.normP[0];
+  const int32_t* clist = bv.bchunks + B * bv.maxc;
+  unsigned long long c_f64 = 0, c_full = 0;
+  for (int ci = 0; ci < nch; ++ci) {
+    const int32_t c = clist[ci];
+    if (t >= bv.cfill[c]) continue;
+    const int64_t slot = (int64_t)c * kPairChunk + t;
+    if (bv.pair_st[slot] != 2) continue;
+    const int64_t u = bv.pair_u[slot];
+    const int32_t jj = bv.pair_j[slot];
+    const int k = bv.k_s[jj];
+    const float nu = ix.normQ[u];
+    const float e = e0 * nu + ix.eps_abs;
+    const float* tk = bv.gl_v + u * K;
+    const int32_t* ti = bv.gl_i + u * K;
+    const float kth = tk[k - 1];
+    float s = bv.pair_s[slot];
+    if (ix.bf16)  // the user's column of the block tile, as the scan reads it
+      s = dot32_col(bv.qs + (int64_t)bv.perm[jj] * ix.d, ix.Qt + B * (int64_t)ix.d * TILE + (u - B * TILE), ix.d);
+    const float es = ix.eps_rel32 * (nu * bv.qn_s[jj]) + ix.eps_abs;
+    const float lo = s - es, hi = s + es;
+    const float csu = ix.cs_inflate * nu;
+    const int cov = bv.gdone[u];
+    const bool short_prefix = cov < ix.m && csu * ix.normP[cov] > lo;
+    bool yes;
+    if (kth - e > hi) {
+      yes = false;
+    } else if (!short_prefix && kth + e <= lo) {
+      yes = true;
+    } else {
+      yes = resolve_pair(ix, bv, u, jj, k, lo, hi, nu, tk, ti, K, short_prefix, c_full);
+      ++c_f64;
+    }
+    if (yes) set_pair_result(bv, ix, u, bv.perm[jj]);
+  }
+  if (bv.ctr) {
+    for (int off = 32; off > 0; off >>= 1) {
+      c_f64 += __shfl_xor(c_f64, off);
+      c_full += __shfl_xor(c_full, off);
+    }
+    if (lane == 0) {
+      if (c_full) atomicAdd(&bv.ctr[C_F64SCAN], c_full);
+      if (c_f64) atomicAdd(&bv.ctr[C_RCHK], c_f64);
     }
   }
 }
@@ -1316,10 +1461,18 @@ void launch_bscan_reset(const DevIndex& ix, const BatchView& bv, hipStream_t s) 
 }
 
 // Bounded table: empty chunk lists before the filter.
-__global__ void k_bclear(int32_t* __restrict__ bcnt, int32_t nB, int32_t* __restrict__ nchunks) {
+__global__ void k_bclear(int32_t* __restrict__ bcnt, int32_t nB, int32_t* __restrict__ nchunks,
+                         int32_t* __restrict__ sg_block, int32_t* __restrict__ sg_count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nB) bcnt[i] = 0;
-  if (i == 0) *nchunks = 0;
+  if (i < nB) {
+    bcnt[i] = 0;
+    sg_block[i] = 0;
+  }
+  if (i == 0) {
+    *nchunks = 0;
+    sg_count[0] = 0;
+    sg_count[1] = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1329,7 +1482,7 @@ void launch_bprep(const DevIndex& ix, const BatchView& bv, const int32_t* ks_dev
                      bv.npairs);
   if (!ix.exact && ix.nB > 0)
     hipLaunchKernelGGL(k_bclear, dim3((ix.nB + 255) / 256), dim3(256), 0, s, bv.bcnt, ix.nB,
-                       bv.nchunks);
+                       bv.nchunks, bv.sg_block, bv.sg_count);
   hipLaunchKernelGGL(k_bsort, dim3(1), dim3(1024), (size_t)(ix.kmax + 1) * kSortBuckets * 4, s,
                      bv.qn, ks_dev, nq, ix.kmax, bv.perm);
   dim3 blk(64, 4);
@@ -1380,17 +1533,32 @@ size_t bscan_lds_bytes(const DevIndex& ix) {
 
 size_t bscan_static_lds() {
   hipFuncAttributes a{};
-  if (hipFuncGetAttributes(&a, (const void*)k_bscan<2>) != hipSuccess) return 16384;
+  if (hipFuncGetAttributes(&a, (const void*)k_bscan<2, false>) != hipSuccess) return 16384;
   return a.sharedSizeBytes;
 }
 
 template <int NV>
 static void bscan_nv(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
   const size_t lds = bscan_lds_bytes(ix);
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_bscan<NV>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-  hipLaunchKernelGGL((k_bscan<NV>), dim3(ix.nB), dim3(256), lds, s, ix, bv);
+  if (lds > 65536) {
+    (void)hipFuncSetAttribute((const void*)k_bscan<NV, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_bscan<NV, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  hipLaunchKernelGGL((k_bscan<NV, false>), dim3(ix.nB), dim3(256), lds, s, ix, bv);
+  // the handed-over users, 64 per workgroup (at most nB groups; the rest
+  // exit), in passes over alternating lists
+  for (int lev = 0; lev < kGroupLevels; ++lev) {
+    BatchView g = bv;
+    g.sg_level = lev;
+    g.sg_last = lev == kGroupLevels - 1;
+    // the list this pass hands over to starts empty (the first is cleared with the chunk)
+    if (lev > 0 && !g.sg_last)
+      hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, g.sg_count + ((lev & 1) ^ 1), (int64_t)1, 0);
+    hipLaunchKernelGGL((k_bscan<NV, true>), dim3(ix.nB), dim3(256), lds, s, ix, g);
+  }
+  hipLaunchKernelGGL(k_bdecide, dim3(ix.nB), dim3(256), 0, s, ix, bv);
 }
 
 void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s) {

@@ -6,6 +6,7 @@ namespace rk {
 
 constexpr int kBatchChunkMax = 4096;  // queries per chunk (single-workgroup sort in LDS)
 constexpr int kPairChunk = 256;       // slots per pair chunk (bounded table)
+constexpr int kUserPairs = 8;         // flagged-pair slots per user in the scan's long pass
 
 // Scan list length per user: k_max + 2 rounded up to a multiple of 4.
 __host__ __device__ inline int bscan_list_len(int kmax) { return (kmax + 2 + 3) / 4 * 4; }
@@ -46,6 +47,21 @@ struct BatchView {
   int32_t* gdone;               // [n_pad] items covered (a multiple of 64); 0 at a call's start
   int32_t carry_in;             // 1: the lists hold the previous chunks' state
   int32_t carry_out;            // 1: later chunks follow (store the lists)
+  // Users still scanning when at most a few of their block are, handed to
+  // passes that scan them in groups of 64 from several blocks (a group pass
+  // hands its own last users to the next): the users of two alternating
+  // lists, a flag per block that handed any over, and each user's pair slots
+  // (count, k, lower and upper bound of f(q,u)); their lists and covered
+  // lengths are in gl_v, gl_i and gdone.
+  int32_t* sg_count;            // [2] users in each list
+  int32_t* sg_users;            // [2][n_pad] their sorted indices
+  int32_t sg_level;             // group pass: reads list sg_level & 1, hands over to the other
+  int32_t sg_last;              // group pass: 1 = the last, scans to the end
+  int32_t* sg_block;            // [nB]
+  int32_t* st_np;               // [n_pad]
+  int32_t* st_pk;               // [n_pad][kUserPairs]
+  float* st_plo;                // [n_pad][kUserPairs]
+  float* st_ph;                 // [n_pad][kUserPairs]
   unsigned long long* ctr;      // statistics or nullptr
 };
 

@@ -106,6 +106,10 @@ struct rk_index {
     int32_t *pair_st = nullptr, *cfill = nullptr, *nchunks = nullptr, *bcnt = nullptr,
             *bchunks = nullptr, *gl_i = nullptr, *gdone = nullptr;
     float* gl_v = nullptr;
+    // users handed to the grouped pass and their pair slots
+    int32_t *sg_count = nullptr, *sg_users = nullptr, *sg_block = nullptr, *st_np = nullptr,
+            *st_pk = nullptr;
+    float *st_plo = nullptr, *st_ph = nullptr;
     int32_t chunk_cap = 0, maxc = 0;
     uint32_t* bits = nullptr;
     unsigned long long* counts = nullptr;
@@ -525,7 +529,8 @@ BatchSizes batch_sizes(const rk_index* h, int32_t chunk) {
   if (!ix.exact)
     b += std::max<int64_t>(pc, 1) * 4 + std::max<int64_t>(z.chunk_cap, 1) * 4 + 4 +
          std::max<int64_t>(ix.nB, 1) * 4 * (1 + z.maxc) +
-         std::max<int64_t>(ix.n_pad, 1) * (8 * (int64_t)bscan_list_len(ix.kmax) + 4);
+         std::max<int64_t>(ix.n_pad, 1) * (8 * (int64_t)bscan_list_len(ix.kmax) + 4) + 4 +
+         std::max<int64_t>(ix.nB, 1) * 4 + std::max<int64_t>(ix.n_pad, 1) * (12 + 12 * kUserPairs) + 4;
   z.bytes = b;
   return z;
 }
@@ -550,10 +555,13 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
                   (void*)b.perm, (void*)b.k_s, (void*)b.npairs, (void*)b.pair_u, (void*)b.pair_j,
                   (void*)b.ks_dev, (void*)b.bits, (void*)b.counts, (void*)b.all,
                   (void*)b.pair_st, (void*)b.cfill, (void*)b.nchunks, (void*)b.bcnt,
-                  (void*)b.bchunks, (void*)b.gl_v, (void*)b.gl_i, (void*)b.gdone})
+                  (void*)b.bchunks, (void*)b.gl_v, (void*)b.gl_i, (void*)b.gdone,
+                  (void*)b.sg_count, (void*)b.sg_users, (void*)b.sg_block, (void*)b.st_np,
+                  (void*)b.st_pk, (void*)b.st_plo, (void*)b.st_ph})
     if (p) h->dfree(p);
   b.pair_st = b.cfill = b.nchunks = b.bcnt = b.bchunks = b.gl_i = b.gdone = nullptr;
-  b.gl_v = nullptr;
+  b.sg_count = b.sg_users = b.sg_block = b.st_np = b.st_pk = nullptr;
+  b.gl_v = b.st_plo = b.st_ph = nullptr;
   const DevIndex& ix = h->ix;
   const BatchSizes z = batch_sizes(h, chunk);
   const int64_t cp = round_up(chunk, TILE), W = bitmap_words(ix.n);
@@ -585,6 +593,14 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
     HIPTRY(h->dalloc(&b.gl_v, nl));
     HIPTRY(h->dalloc(&b.gl_i, nl));
     HIPTRY(h->dalloc(&b.gdone, std::max<int64_t>(ix.n_pad, 1)));
+    const int64_t np1 = std::max<int64_t>(ix.n_pad, 1);
+    HIPTRY(h->dalloc(&b.sg_count, 2));
+    HIPTRY(h->dalloc(&b.sg_users, 2 * np1));
+    HIPTRY(h->dalloc(&b.sg_block, std::max<int64_t>(ix.nB, 1)));
+    HIPTRY(h->dalloc(&b.st_np, np1));
+    HIPTRY(h->dalloc(&b.st_pk, np1 * kUserPairs));
+    HIPTRY(h->dalloc(&b.st_plo, np1 * kUserPairs));
+    HIPTRY(h->dalloc(&b.st_ph, np1 * kUserPairs));
   }
   HIPTRY(hipMemsetAsync(b.bits, 0, (size_t)chunk * std::max<int64_t>(W, 1) * 4, h->stream));
   HIPTRY(hipMemsetAsync(b.counts, 0, (size_t)chunk * 8, h->stream));
@@ -652,6 +668,8 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
     bv.pair_st = b.pair_st; bv.cfill = b.cfill; bv.nchunks = b.nchunks;
     bv.chunk_cap = b.chunk_cap; bv.maxc = b.maxc; bv.bcnt = b.bcnt; bv.bchunks = b.bchunks;
     bv.gl_v = b.gl_v; bv.gl_i = b.gl_i; bv.gdone = b.gdone;
+    bv.sg_count = b.sg_count; bv.sg_users = b.sg_users; bv.sg_block = b.sg_block;
+    bv.st_np = b.st_np; bv.st_pk = b.st_pk; bv.st_plo = b.st_plo; bv.st_ph = b.st_ph;
     bv.carry_in = c0 > 0;
     bv.carry_out = c0 + nc < nq;
     if (c0 == 0 && bv.carry_out) launch_bscan_reset(ix, bv, s);  // the scan state is per call
@@ -1069,7 +1087,7 @@ rk_status rk_index_stats(const rk_index* hc, rk_stats* o) {
   o->blocks_visited = c[C_BLOCKS]; o->blocks_pruned = c[C_PRUNED]; o->users_evaluated = c[C_USERS];
   o->lemma1_no = c[C_L1NO]; o->lemma2_yes = c[C_L2YES]; o->table_yes = c[C_TYES];
   o->survivors = c[C_SURV]; o->scan_items = c[C_SCAN]; o->rechecks = c[C_RCHK]; o->results = c[C_RES];
-  o->scan_long = c[C_LONG]; o->scan_full_f64 = c[C_F64SCAN];
+  o->scan_long = c[C_LONG]; o->scan_full_f64 = c[C_F64SCAN]; o->scan_handoff = c[C_HANDOFF];
   return RK_OK;
 }
 

@@ -63,7 +63,7 @@ class Stats(ctypes.Structure):
                 ("survivors", ctypes.c_int64), ("scan_items", ctypes.c_int64),
                 ("rechecks", ctypes.c_int64), ("results", ctypes.c_int64),
                 ("scan_long", ctypes.c_int64), ("scan_full_f64", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 6)]
+                ("scan_handoff", ctypes.c_int64), ("reserved", ctypes.c_int64 * 5)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -248,6 +248,47 @@ def test_grouped_scan_early_exit(prec):
     idx.free()
 
 
+def handoff_case(rng):
+    # 32 users along +x and 224 along +y, mixed in every block (similar
+    # norms); 8 large items along +y (the lower-bound prefix: the y users'
+    # pairs end at Lemma 1), 40,000 items of norm about 3 nearly orthogonal
+    # to x and y, and 40 small ones.  Queries along +x beat almost every item
+    # for the x users, whose scans run to the small items: each block has at
+    # most 8 users scanning, with most of the catalog ahead.
+    d = 16
+    nx, ny = 32, 224
+    Q = 0.05 * rng.standard_normal((nx + ny, d))
+    Q[:nx, 0] += 1 + 0.1 * rng.random(nx)
+    Q[nx:, 1] += 1 + 0.1 * rng.random(ny)
+    Q = Q[rng.permutation(nx + ny)]
+    top = 0.05 * rng.standard_normal((8, d))
+    top[:, 1] += 5
+    mid = rng.standard_normal((40000, d))
+    mid[:, :2] *= 0.02
+    mid *= (2.5 + rng.random((40000, 1))) / np.linalg.norm(mid, axis=1, keepdims=True)
+    small = 0.3 * rng.standard_normal((40, d))
+    P = np.vstack([top, mid, small]).astype(np.float32)
+    qs = 0.05 * rng.standard_normal((20, d))
+    qs[:, 0] += 0.9 + 0.2 * rng.random(20)
+    ks = rng.integers(1, 9, 20).astype(np.int32)
+    return Q.astype(np.float32), P, qs.astype(np.float32), ks
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_grouped_scan_handoff_to_group_passes(prec):
+    # the last users of a block still scanning with most of a 625-tile
+    # catalog ahead are handed to group passes of users from several blocks,
+    # and their pairs decided from the final lists
+    Q, P, qs, ks = handoff_case(np.random.default_rng(21))
+    idx = Index.build(Q, P, 8, lb_items=8, precision=prec)
+    idx.set_counting(True)
+    off, ids = idx.reverse_kmips_batch(qs, ks)
+    st = idx.stats()
+    check_csr(Q, P, qs, ks, off, ids)
+    assert st["scan_handoff"] > 0
+    idx.free()
+
+
 # --- limits: largest k_max, widest d ----------------------------------------
 
 @pytest.mark.parametrize("lb,prec", [(0, "fp32"), (130, "fp32"), (130, "bf16")])
