@@ -11,6 +11,12 @@ traffic as null).
 
     python -m paper_2110_07131_amd.profiling --fetch DIR1 --write DIR2 \\
         --kernel k_bfilter --copy-mb 1024 --key plain/fp32/exact --out profiles/traffic.json
+
+A phase of several kernels (the bounded table's scan: the block pass, the
+group passes and k_bdecide, launched once per query chunk) is measured with
+--match (all its dispatches) and --per (the dispatch that counts phases):
+the traffic per phase is the sum over the matching dispatches divided by the
+number of phases.
 """
 from __future__ import annotations
 
@@ -76,11 +82,18 @@ def read_counter(run_dir: str, counter: str) -> list[tuple[str, float]]:
     return list(per.values())
 
 
-def kernel_average(rows, pattern: str) -> tuple[float, int]:
+def kernel_average(rows, pattern: str, per: str | None = None) -> tuple[float, int]:
+    """Average reading per dispatch of `pattern`; with `per`, the sum over the
+    dispatches of `pattern` per dispatch of `per` (a phase of several kernels)."""
     vals = [v for n, v in rows if re.search(pattern, n)]
     if not vals:
         raise ValueError(f"no dispatch of {pattern}")
-    return sum(vals) / len(vals), len(vals)
+    if per is None:
+        return sum(vals) / len(vals), len(vals)
+    count = sum(1 for n, _ in rows if re.search(per, n))
+    if count == 0:
+        raise ValueError(f"no dispatch of {per}")
+    return sum(vals) / count, count
 
 
 def copy_factor(rows, copy_bytes: int) -> tuple[float, float]:
@@ -98,7 +111,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
-    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--kernel", required=True, help="label (and default dispatch pattern)")
+    ap.add_argument("--match", default=None, help="regex of the dispatches summed (default: --kernel)")
+    ap.add_argument("--per", default=None, help="regex of the dispatch counting phases")
     ap.add_argument("--copy-mb", type=int, required=True)
     ap.add_argument("--key", required=True, help="workload/precision/table, e.g. plain/fp32/exact")
     ap.add_argument("--command", default="")
@@ -108,10 +123,12 @@ def main():
     fr, wr = read_counter(a.fetch, "FETCH_SIZE"), read_counter(a.write, "WRITE_SIZE")
     ff, fmeas = copy_factor(fr, nbytes)
     wf, wmeas = copy_factor(wr, nbytes)
-    fk, nf = kernel_average(fr, a.kernel)
-    wk, nw = kernel_average(wr, a.kernel)
+    pat = a.match or a.kernel
+    fk, nf = kernel_average(fr, pat, a.per)
+    wk, nw = kernel_average(wr, pat, a.per)
     entry = {
         "kernel": a.kernel, "key": a.key, "source_hash": source_hash(a.kernel),
+        "match": pat, "per": a.per or pat,
         "fetch_kib_per_launch": fk, "write_kib_per_launch": wk, "launches": [nf, nw],
         "copy_mb": a.copy_mb, "copy_fetch_kib": fmeas, "copy_write_kib": wmeas,
         "fetch_factor": ff, "write_factor": wf,

@@ -74,6 +74,11 @@ def test_traffic_summary_from_counter_files(tmp_path):
     assert n == 2 and avg == pytest.approx(12000.0)
     with pytest.raises(ValueError):
         profiling.kernel_average(fr, "k_bscan")
+    # a phase: everything matching, per dispatch of the phase's first kernel
+    rows = [("k_bscan<4, false>", 10.0), ("k_bscan<4, true>", 1.0), ("k_bdecide", 2.0),
+            ("k_bscan<4, false>", 20.0), ("k_bscan<4, true>", 3.0), ("k_bdecide", 4.0)]
+    tot, n = profiling.kernel_average(rows, "k_bscan|k_bdecide", r"k_bscan<\d+, false>")
+    assert n == 2 and tot == pytest.approx(20.0)
 
 
 def test_source_hash_is_stable_per_kernel():
