@@ -163,8 +163,10 @@ __device__ __forceinline__ bool decide_f64(const DevIndex& ix, const BatchView& 
 // walks only the tiles that have a live query.  All four waves work on the
 // same query tile, staged in LDS: wave w computes the 32x32 quarter (user
 // half w&1, query half w>>1) with MFMA, so a lane holds one user and 16
-// queries.  While a tile is processed the next live tile is being fetched
-// into registers; it is written to LDS between two barriers.  The epilogue
+// queries.  While a tile is processed the next live tile is being fetched:
+// bf16 tiles straight into a second LDS buffer (global_load_lds, one barrier
+// per tile), float32 tiles into registers, written to LDS between two
+// barriers (a second float32 buffer would cost a workgroup per CU).  The epilogue
 // is the certified Lemma 1 test only; every pair it cannot reject is
 // appended to the pair list, decided afterwards by the recheck or the scan.
 constexpr int PF_VEC = 16;  // prefetch registers per thread: 16 x 16 bytes (64 KiB tiles)
@@ -205,13 +207,37 @@ __device__ __forceinline__ void commit_tile(unsigned char* qbuf, float* meta_n, 
   else if (t < 2 * TILE) meta_k[t - TILE] = pf_k;
 }
 
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Query tile T and its metadata straight from global memory into LDS
+// (global_load_lds: lane l of a wave writes 16 bytes at the wave's LDS base +
+// 16 l, so one instruction moves 1 KiB): wave w moves the 1 KiB chunks w,
+// w+4, ...; waves 0 and 1 move the 64 norms and k values.  The data is there
+// once the issuing wave has waited for its vector memory operations.
+__device__ __forceinline__ void issue_tile(const unsigned char* __restrict__ qsrc, const BatchView& bv,
+                                           int T, int tile_bytes, int lane, int wave,
+                                           unsigned char* qdst, float* mn_dst, int32_t* mk_dst) {
+  const unsigned char* src = qsrc + (int64_t)T * tile_bytes;
+  for (int c = wave; c * 1024 < tile_bytes; c += 4) {
+    if (c * 1024 + lane * 16 < tile_bytes)
+      __builtin_amdgcn_global_load_lds((const void*)(src + c * 1024 + lane * 16),
+                                       (lds_void_t*)(qdst + c * 1024), 16, 0, 0);
+  }
+  if (wave == 0)
+    __builtin_amdgcn_global_load_lds((const void*)(bv.qn_s + (int64_t)T * TILE + lane),
+                                     (lds_void_t*)mn_dst, 4, 0, 0);
+  else if (wave == 1)
+    __builtin_amdgcn_global_load_lds((const void*)(bv.k_s + (int64_t)T * TILE + lane),
+                                     (lds_void_t*)mk_dst, 4, 0, 0);
+}
+
 __device__ __forceinline__ int quarter_row(int qhalf, int half, int r) {
   return qhalf * 32 + (r / 4) * 8 + half * 4 + (r % 4);
 }
 
 // Occupancy: float32 tiles of d <= 64 (NV <= 4) run 4 waves per SIMD (a
-// 32-byte spill, 2% faster measured); wider tiles keep their prefetch
-// registers and 2-3 waves.
+// 32-byte spill, 2% faster measured); wider float32 tiles keep their
+// prefetch registers and 2-3 waves; bf16 has no prefetch registers.
 template <bool BF16, int NV>
 __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(DevIndex ix, BatchView bv) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -228,12 +254,18 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   unsigned char* p = lds_raw;
   unsigned char* ubuf = p;
   p += (tile_bytes + 15) / 16 * 16;
-  unsigned char* qbuf = p;
+  // query tile buffers: bf16 two, alternating (filled straight from global
+  // memory while the other is used); float32 one, filled from prefetch
+  // registers (a second float32 buffer would cost a workgroup per CU)
+  unsigned char* qbuf2[2];
+  qbuf2[0] = p;
   p += (tile_bytes + 15) / 16 * 16;
-  float* meta_n = (float*)p;
-  p += TILE * 4;
-  int32_t* meta_k = (int32_t*)p;
-  p += TILE * 4;
+  qbuf2[1] = p;
+  if (BF16) p += (tile_bytes + 15) / 16 * 16;
+  float* meta_n2 = (float*)p;    // [2][64] norms of the tile's queries
+  p += 2 * TILE * 4;
+  int32_t* meta_k2 = (int32_t*)p;  // [2][64] their k
+  p += 2 * TILE * 4;
   unsigned long long* masks = (unsigned long long*)p;
   p += (kBatchChunkMax / TILE) * 8;
   float* Ll = (float*)p;
@@ -294,25 +326,39 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   const int32_t orig_u = valid ? ix.permQ[u] : 0;
   unsigned long long c_users = 0, c_rest = 0, c_yes = 0;
 
-  // prefetch registers for the next tile (tile bytes + 512 bytes of metadata)
-  u32x4 pf[NV];
+  const unsigned char* qsrc = BF16 ? (const unsigned char*)bv.qb : (const unsigned char*)bv.qt;
+  // float32: prefetch registers for the next tile (tile bytes + 512 bytes of metadata)
+  u32x4 pf[BF16 ? 1 : NV];
   float pf_n = 0.f;
   int32_t pf_k = 0;
-  const u32x4* qsrc = BF16 ? (const u32x4*)bv.qb : (const u32x4*)bv.qt;
 
   // bounded table: this wave's current pair chunk and its fill
   int ccur = -1, cfill_w = kPairChunk;
 
-  int T = next_live(masks, 0, nT);
-  if (T < nT) {
-    stage_tile(qsrc, bv, T, tile_vecs, t, pf, pf_n, pf_k);
-    commit_tile(qbuf, meta_n, meta_k, tile_vecs, t, pf, pf_n, pf_k);
-  }
-  __syncthreads();
+  int T = next_live(masks, 0, nT), slot = 0;
   int Tn = next_live(masks, T + 1, nT);
-  if (Tn < nT) stage_tile(qsrc, bv, Tn, tile_vecs, t, pf, pf_n, pf_k);
+  if constexpr (BF16) {
+    if (T < nT) issue_tile(qsrc, bv, T, tile_bytes, lane, wave, qbuf2[0], meta_n2, meta_k2);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  } else {
+    if (T < nT) {
+      stage_tile((const u32x4*)qsrc, bv, T, tile_vecs, t, pf, pf_n, pf_k);
+      commit_tile(qbuf2[0], meta_n2, meta_k2, tile_vecs, t, pf, pf_n, pf_k);
+    }
+    __syncthreads();
+    if (Tn < nT) stage_tile((const u32x4*)qsrc, bv, Tn, tile_vecs, t, pf, pf_n, pf_k);
+  }
 
   while (T < nT) {
+    // bf16: the next live tile streams into the other buffer (read last in
+    // the previous step, which every wave has finished) while this one is used
+    if (BF16 && Tn < nT)
+      issue_tile(qsrc, bv, Tn, tile_bytes, lane, wave, qbuf2[slot ^ 1], meta_n2 + (slot ^ 1) * TILE,
+                 meta_k2 + (slot ^ 1) * TILE);
+    const unsigned char* qbuf = qbuf2[slot];
+    const float* meta_n = meta_n2 + slot * TILE;
+    const int32_t* meta_k = meta_k2 + slot * TILE;
     const unsigned long long mask = masks[T];
     // this wave's query half may have no live query at all
     const uint32_t hmask = (uint32_t)(mask >> (qhalf * 32));
@@ -504,13 +550,22 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
 
     }  // hmask
 
-    // ---- next tile: prefetched registers -> LDS
-    __syncthreads();
-    if (Tn < nT) commit_tile(qbuf, meta_n, meta_k, tile_vecs, t, pf, pf_n, pf_k);
-    T = Tn;
-    Tn = next_live(masks, T + 1, nT);
-    __syncthreads();
-    if (Tn < nT) stage_tile(qsrc, bv, Tn, tile_vecs, t, pf, pf_n, pf_k);
+    // ---- next tile: bf16 landed in the other buffer; float32 from the
+    // prefetch registers into the one buffer
+    if constexpr (BF16) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      T = Tn;
+      Tn = next_live(masks, T + 1, nT);
+      slot ^= 1;
+    } else {
+      __syncthreads();
+      if (Tn < nT) commit_tile(qbuf2[0], meta_n2, meta_k2, tile_vecs, t, pf, pf_n, pf_k);
+      T = Tn;
+      Tn = next_live(masks, T + 1, nT);
+      __syncthreads();
+      if (Tn < nT) stage_tile((const u32x4*)qsrc, bv, Tn, tile_vecs, t, pf, pf_n, pf_k);
+    }
   }
   if (!ix.exact && lane == 0 && ccur >= 0 && ccur < bv.chunk_cap) bv.cfill[ccur] = cfill_w;
 
@@ -1493,7 +1548,7 @@ void launch_bprep(const DevIndex& ix, const BatchView& bv, const int32_t* ks_dev
 
 size_t bfilter_lds_bytes(const DevIndex& ix) {
   const size_t tile = ix.bf16 ? (size_t)(ix.d16 / 8) * TILE * 16 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
-  return 2 * ((tile + 15) / 16 * 16) + 2 * TILE * 4 + (kBatchChunkMax / TILE) * 8 +
+  return (ix.bf16 ? 3 : 2) * ((tile + 15) / 16 * 16) + 4 * TILE * 4 + (kBatchChunkMax / TILE) * 8 +
          2 * (size_t)ix.kmax * TILE * 4 + (size_t)ix.kmax * 8;
 }
 
