@@ -164,9 +164,9 @@ __device__ __forceinline__ bool decide_f64(const DevIndex& ix, const BatchView& 
 // same query tile, staged in LDS: wave w computes the 32x32 quarter (user
 // half w&1, query half w>>1) with MFMA, so a lane holds one user and 16
 // queries.  While a tile is processed the next live tile is being fetched:
-// bf16 tiles straight into a second LDS buffer (global_load_lds, one barrier
-// per tile), float32 tiles into registers, written to LDS between two
-// barriers (a second float32 buffer would cost a workgroup per CU).  The epilogue
+// small bf16 tiles (d <= 64) straight into a second LDS buffer
+// (global_load_lds, one barrier per tile), other tiles into registers,
+// written to LDS between two barriers.  The epilogue
 // is the certified Lemma 1 test only; every pair it cannot reject is
 // appended to the pair list, decided afterwards by the recheck or the scan.
 constexpr int PF_VEC = 16;  // prefetch registers per thread: 16 x 16 bytes (64 KiB tiles)
@@ -236,8 +236,8 @@ __device__ __forceinline__ int quarter_row(int qhalf, int half, int r) {
 }
 
 // Occupancy: float32 tiles of d <= 64 (NV <= 4) run 4 waves per SIMD (a
-// 32-byte spill, 2% faster measured); wider float32 tiles keep their
-// prefetch registers and 2-3 waves; bf16 has no prefetch registers.
+// 32-byte spill, 2% faster measured); wider tiles keep their prefetch
+// registers and 2-3 waves.
 template <bool BF16, int NV>
 __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(DevIndex ix, BatchView bv) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -254,14 +254,17 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   unsigned char* p = lds_raw;
   unsigned char* ubuf = p;
   p += (tile_bytes + 15) / 16 * 16;
-  // query tile buffers: bf16 two, alternating (filled straight from global
-  // memory while the other is used); float32 one, filled from prefetch
-  // registers (a second float32 buffer would cost a workgroup per CU)
+  // query tile buffers: small bf16 tiles two, alternating (filled straight
+  // from global memory while the other is used); otherwise one, filled from
+  // prefetch registers (a second float32 buffer would cost a workgroup per
+  // CU; and as the compiler waits for the direct loads before the next LDS
+  // read, larger tiles lose the overlap: 42-66% slower at d = 100-200)
+  constexpr bool LDSD = BF16 && NV <= 2;
   unsigned char* qbuf2[2];
   qbuf2[0] = p;
   p += (tile_bytes + 15) / 16 * 16;
   qbuf2[1] = p;
-  if (BF16) p += (tile_bytes + 15) / 16 * 16;
+  if (LDSD) p += (tile_bytes + 15) / 16 * 16;
   float* meta_n2 = (float*)p;    // [2][64] norms of the tile's queries
   p += 2 * TILE * 4;
   int32_t* meta_k2 = (int32_t*)p;  // [2][64] their k
@@ -328,7 +331,7 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
 
   const unsigned char* qsrc = BF16 ? (const unsigned char*)bv.qb : (const unsigned char*)bv.qt;
   // float32: prefetch registers for the next tile (tile bytes + 512 bytes of metadata)
-  u32x4 pf[BF16 ? 1 : NV];
+  u32x4 pf[LDSD ? 1 : NV];
   float pf_n = 0.f;
   int32_t pf_k = 0;
 
@@ -337,7 +340,7 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
 
   int T = next_live(masks, 0, nT), slot = 0;
   int Tn = next_live(masks, T + 1, nT);
-  if constexpr (BF16) {
+  if constexpr (LDSD) {
     if (T < nT) issue_tile(qsrc, bv, T, tile_bytes, lane, wave, qbuf2[0], meta_n2, meta_k2);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -353,7 +356,7 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   while (T < nT) {
     // bf16: the next live tile streams into the other buffer (read last in
     // the previous step, which every wave has finished) while this one is used
-    if (BF16 && Tn < nT)
+    if (LDSD && Tn < nT)
       issue_tile(qsrc, bv, Tn, tile_bytes, lane, wave, qbuf2[slot ^ 1], meta_n2 + (slot ^ 1) * TILE,
                  meta_k2 + (slot ^ 1) * TILE);
     const unsigned char* qbuf = qbuf2[slot];
@@ -552,7 +555,7 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
 
     // ---- next tile: bf16 landed in the other buffer; float32 from the
     // prefetch registers into the one buffer
-    if constexpr (BF16) {
+    if constexpr (LDSD) {
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       T = Tn;
@@ -1548,7 +1551,8 @@ void launch_bprep(const DevIndex& ix, const BatchView& bv, const int32_t* ks_dev
 
 size_t bfilter_lds_bytes(const DevIndex& ix) {
   const size_t tile = ix.bf16 ? (size_t)(ix.d16 / 8) * TILE * 16 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
-  return (ix.bf16 ? 3 : 2) * ((tile + 15) / 16 * 16) + 4 * TILE * 4 + (kBatchChunkMax / TILE) * 8 +
+  const bool ldsd = ix.bf16 && (tile / 16 + 255) / 256 <= 2;  // the kernel's direct-load case (NV <= 2)
+  return (ldsd ? 3 : 2) * ((tile + 15) / 16 * 16) + 4 * TILE * 4 + (kBatchChunkMax / TILE) * 8 +
          2 * (size_t)ix.kmax * TILE * 4 + (size_t)ix.kmax * 8;
 }
 

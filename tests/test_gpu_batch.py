@@ -289,6 +289,25 @@ def test_grouped_scan_handoff_to_group_passes(prec):
     idx.free()
 
 
+def test_grouped_scan_handoff_with_lists_carried_across_chunks():
+    # 4,200 queries (two query chunks) on the hand-off catalog: users handed
+    # to group passes in the first chunk start the second from the lists and
+    # coverage the group passes stored
+    Q, P, qs0, _ = handoff_case(np.random.default_rng(22))
+    rng = np.random.default_rng(23)
+    qs = np.ascontiguousarray(qs0[rng.integers(0, len(qs0), 4200)] +
+                              0.01 * rng.standard_normal((4200, qs0.shape[1])).astype(np.float32))
+    ks = rng.integers(1, 9, 4200).astype(np.int32)
+    idx = Index.build(Q, P, 8, lb_items=8)
+    idx.set_counting(True)
+    off, ids = idx.reverse_kmips_batch(qs, ks)
+    st = idx.stats()
+    assert st["scan_handoff"] > 0
+    for i in list(range(0, 4200, 97)) + [4095, 4096, 4199]:
+        assert np.array_equal(ids[off[i]:off[i + 1]], oracle.brute(Q, P, qs[i], int(ks[i]))), i
+    idx.free()
+
+
 # --- limits: largest k_max, widest d ----------------------------------------
 
 @pytest.mark.parametrize("lb,prec", [(0, "fp32"), (130, "fp32"), (130, "bf16")])
