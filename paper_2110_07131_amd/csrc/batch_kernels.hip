@@ -638,8 +638,12 @@ __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView b
 //   the prefix has fewer than k items); otherwise the float64 scan decides.
 // Short pass: the first kShortTiles item tiles, then every pair is read once;
 // most pairs end here.  The others are flagged; the scan then continues, for
-// the users that have such pairs only, up to each user's largest limit, and
-// the flagged pairs are decided at the end.
+// the users that have such pairs only, until each of their pairs is either
+// decided no (k list entries certainly above it: Algorithm 2's early exit)
+// or covered to its limit, and the flagged pairs are decided at the end.
+// The last users of a block still scanning with a long way to go are handed
+// to group passes that continue 64 such users from any blocks at once.  The
+// lists and their coverage carry over to the next query chunk of the call.
 constexpr int kShortTiles = 4;
 constexpr int kFlagCap = 1024;  // flagged pairs listed in LDS per block
 constexpr int kHandoff = 8;     // at most this many users of a block still scanning: hand them over

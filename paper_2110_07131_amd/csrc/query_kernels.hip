@@ -190,6 +190,9 @@ template <bool BF16>
 __global__ void __launch_bounds__(256) k_verify(DevIndex ix, const float* __restrict__ q,
                                                 int32_t k, QueryWS ws) {
   const int lane = threadIdx.x & 63;
+  // float32: the survivor's user row, per wave, read as broadcasts (d <= 512)
+  __shared__ __align__(16) float urow_s[4][BF16 ? 4 : 512];
+  float* uw = urow_s[threadIdx.x >> 6];
   const int nsurv = ws.cnt[0];
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   const float nq = *ws.qnorm;
@@ -214,21 +217,35 @@ __global__ void __launch_bounds__(256) k_verify(DevIndex ix, const float* __rest
     const float* urow = ix.Qrow + r * ix.d;
     int64_t scanned = 0;
     const int64_t ub = r / TILE, ul = r % TILE;
+    if (!BF16) {
+      for (int c = lane; c < ix.d; c += 64) uw[c] = urow[c];
+      __builtin_amdgcn_wave_barrier();
+    }
     for (int64_t t0 = 0; t0 < stop && beats < k; t0 += TILE) {
       const int64_t j = t0 + lane;
       const bool inb = j < stop;
       float g = 0.f;
       if (!BF16) {
-        const float* u = ix.Qt + ub * (int64_t)ix.d * TILE + ul;
+        // sixteen coordinates of item loads in flight (coalesced rows of the
+        // item tile), the user's coordinates from LDS
         const float* p = ix.Pt + (t0 / TILE) * (int64_t)ix.d * TILE + lane;
-        float a0 = 0.f, a1 = 0.f;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
         int c = 0;
-        for (; c + 2 <= ix.d; c += 2) {
-          a0 = fmaf(u[c * TILE], p[c * TILE], a0);
-          a1 = fmaf(u[(c + 1) * TILE], p[(c + 1) * TILE], a1);
+        for (; c + 16 <= ix.d; c += 16) {
+          float pv[16];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) pv[i] = p[(c + i) * TILE];
+#pragma unroll
+          for (int i = 0; i < 16; i += 4) {
+            const float4 u4 = *(const float4*)(uw + c + i);
+            a0 = fmaf(u4.x, pv[i], a0);
+            a1 = fmaf(u4.y, pv[i + 1], a1);
+            a2 = fmaf(u4.z, pv[i + 2], a2);
+            a3 = fmaf(u4.w, pv[i + 3], a3);
+          }
         }
-        if (c < ix.d) a0 = fmaf(u[c * TILE], p[c * TILE], a0);
-        g = a0 + a1;
+        for (; c < ix.d; ++c) a0 = fmaf(uw[c], p[c * TILE], a0);
+        g = (a0 + a1) + (a2 + a3);
       } else {
         const int G = ix.d16 / 8;
         const uint4* u = (const uint4*)(ix.Qb + (ub * G * TILE + ul) * 8);
@@ -260,6 +277,7 @@ __global__ void __launch_bounds__(256) k_verify(DevIndex ix, const float* __rest
       scanned += (stop - t0 < TILE) ? (stop - t0) : TILE;
     }
     const bool yes = beats < k;
+    if (!BF16) __builtin_amdgcn_wave_barrier();  // uw is rewritten for the next survivor
     if (yes && lane == 0) set_result(ws, ix, r);
     if (lane == 0) {
       trace(ws, ix, r,
