@@ -79,7 +79,12 @@ typedef struct {
                              of undecided (user, query) pairs per chunk; pairs
                              beyond it are decided in float64 inside the
                              filter kernel (a test hook for that path) */
-    int32_t reserved[5];
+    int32_t handoff_tiles; /* 0 = default (512).  Bounded table, batched scan:
+                             the last users of a block (or group) still
+                             scanning are handed to a group pass of users from
+                             several blocks only with more than this many
+                             64-item tiles left (a tuning and test hook) */
+    int32_t reserved[4];
 } rk_build_opts;
 
 /* Counters and sizes of an index.  Query counters accumulate over every

@@ -649,9 +649,9 @@ constexpr int kFlagCap = 1024;  // flagged pairs listed in LDS per block
 constexpr int kHandoff = 8;     // at most this many users of a block still scanning: hand them over
 constexpr int kGroupHandoff = 16;  // the same for a group pass (but the last)
 constexpr int kGroupLevels = 2;    // group passes
-// ... and only with more than this many item tiles left (shorter tails cost
-// less where they are than the extra passes)
-constexpr int kHandoffMinTiles = 512;
+// ... and only with more than ix.handoff_tiles item tiles left (512 unless
+// the index options say otherwise: shorter tails cost less where they are
+// than the extra passes)
 
 
 template <int NV>
@@ -901,7 +901,7 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
       if (!all_users && !(more_w[0] | more_w[1] | more_w[2] | more_w[3])) break;
       // (a group hands over only if it started with more than twice as many)
       if (!all_users && (!GROUP || (!bv.sg_last && nopen0 > 2 * kGroupHandoff)) &&
-          ix.mB - I > kHandoffMinTiles &&
+          ix.mB - I > ix.handoff_tiles &&
           __popcll(__ballot(open[lane] != 0)) <= (GROUP ? kGroupHandoff : kHandoff)) {
         handoff = true;
         break;
@@ -1283,7 +1283,7 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
     for (int i = 0; i < TILE; ++i)
       if (open[i]) tmin = min(tmin, Cov[i]), ++nopen;
     nopen0 = nopen;
-    if (!GROUP && nopen <= kHandoff && ix.mB - tmin / TILE > kHandoffMinTiles) handoff = nopen > 0;
+    if (!GROUP && nopen <= kHandoff && ix.mB - tmin / TILE > ix.handoff_tiles) handoff = nopen > 0;
     else if (tmin < INT_MAX) scan_tiles(tmin / TILE, (int)ix.mB, false);
     if (handoff) {
       // users still scanning: a place in the next group pass, and from a

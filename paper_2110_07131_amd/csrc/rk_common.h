@@ -80,6 +80,7 @@ struct DevIndex {
   float eps_abs;         // absolute slack (underflow)
   float cs_inflate;      // 1 + gamma64_d + slack: f(p,u) <= cs_inflate*|u|^*|p|^
   float eps_rel32;       // eps_rel of float32 products (the verification pass)
+  int32_t handoff_tiles; // batched scan: hand over only with more tiles than this left
 };
 
 // f(x, y) in float64, index order, from two contiguous float32 rows: the

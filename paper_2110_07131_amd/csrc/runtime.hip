@@ -165,6 +165,7 @@ rk_status check_opts(const rk_build_opts& o) {
     return fail(RK_E_INVAL, "margin_rel must be finite, >= 0 and < 0.5");
   if (o.cand_cap < 0) return fail(RK_E_INVAL, "cand_cap must be >= 0");
   if (o.pair_cap < 0) return fail(RK_E_INVAL, "pair_cap must be >= 0");
+  if (o.handoff_tiles < 0) return fail(RK_E_INVAL, "handoff_tiles must be >= 0");
   if (o.device < 0) return fail(RK_E_INVAL, "device must be >= 0");
   return RK_OK;
 }
@@ -302,6 +303,7 @@ rk_status build_impl(const float* Q, int64_t n, const float* P, int64_t m, int32
   const double eps = std::max(ix.bf16 ? eps_bf16(d) : eps_fp32(d), o.margin_rel);
   ix.eps_rel = f32_up(eps);
   ix.eps_rel32 = f32_up(h->eps32);
+  ix.handoff_tiles = h->opts.handoff_tiles > 0 ? h->opts.handoff_tiles : 512;
   ix.eps_abs = std::ldexp((double)(d + 2), -124);
   ix.cs_inflate = f32_up(1.0 + gamma_(d, 0x1p-53) + 8 * 0x1p-24);
 

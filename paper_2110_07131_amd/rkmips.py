@@ -46,7 +46,7 @@ class BuildOpts(ctypes.Structure):
                 ("block_size", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("margin_rel", ctypes.c_double), ("cand_cap", ctypes.c_int32),
                 ("auto_rebuild", ctypes.c_int32), ("pair_cap", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("handoff_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -169,7 +169,7 @@ def _check(status: int):
 
 
 def build_opts(precision="fp32", lb_items=0, device=0, margin_rel=0.0, cand_cap=0,
-               auto_rebuild=False, pair_cap=0) -> BuildOpts:
+               auto_rebuild=False, pair_cap=0, handoff_tiles=0) -> BuildOpts:
     o = BuildOpts()
     lib().rk_build_opts_default(ctypes.byref(o))
     o.precision = {"fp32": RK_FP32, "bf16": RK_BF16}[precision] if isinstance(precision, str) else int(precision)
@@ -179,6 +179,7 @@ def build_opts(precision="fp32", lb_items=0, device=0, margin_rel=0.0, cand_cap=
     o.cand_cap = int(cand_cap)
     o.auto_rebuild = 1 if auto_rebuild else 0
     o.pair_cap = int(pair_cap)
+    o.handoff_tiles = int(handoff_tiles)
     return o
 
 

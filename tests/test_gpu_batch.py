@@ -308,6 +308,37 @@ def test_grouped_scan_handoff_with_lists_carried_across_chunks():
     idx.free()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_grouped_scan_handoff_on_short_catalogs(prec):
+    # handoff_tiles = 1: blocks hand over their last users (and group passes
+    # theirs, to the second pass) with any tile left, on a random workload
+    w = datagen.workload(900, 2500, 12, 0.7, 60, seed=31)
+    rng = np.random.default_rng(31)
+    ks = rng.integers(1, 9, len(w.qidx)).astype(np.int32)
+    idx = Index.build(w.Q, w.P, 8, lb_items=10, precision=prec, handoff_tiles=1)
+    idx.set_counting(True)
+    off, ids = idx.reverse_kmips_batch(w.queries, ks)
+    st = idx.stats()
+    check_csr(w.Q, w.P, w.queries, ks, off, ids)
+    assert st["scan_handoff"] > 0
+    idx.free()
+
+
+def test_grouped_scan_handoff_on_short_catalogs_several_chunks():
+    w = datagen.workload(500, 2500, 12, 0.7, 2500, seed=32)
+    rng = np.random.default_rng(32)
+    pick = rng.integers(0, 2500, 4300)
+    qs = np.ascontiguousarray(w.P[pick])
+    ks = rng.integers(1, 9, len(qs)).astype(np.int32)
+    idx = Index.build(w.Q, w.P, 8, lb_items=10, handoff_tiles=1)
+    idx.set_counting(True)
+    off, ids = idx.reverse_kmips_batch(qs, ks)
+    assert idx.stats()["scan_handoff"] > 0
+    for i in list(range(0, 4300, 29)) + [4095, 4096, 4299]:
+        assert np.array_equal(ids[off[i]:off[i + 1]], oracle.brute(w.Q, w.P, qs[i], int(ks[i]))), i
+    idx.free()
+
+
 # --- limits: largest k_max, widest d ----------------------------------------
 
 @pytest.mark.parametrize("lb,prec", [(0, "fp32"), (130, "fp32"), (130, "bf16")])
