@@ -39,6 +39,8 @@ def parse():
                     help="|P'| of the lower-bound arrays; 0 = all items (exact table)")
     ap.add_argument("--latency-queries", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--handoff-tiles", type=int, default=0,
+                    help="index option handoff_tiles (bounded table; 0 = the library default)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -283,7 +285,8 @@ def main():
           file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    idx = Index.build(w.Q, w.P, kmax, precision=args.precision, lb_items=args.lb_items)
+    idx = Index.build(w.Q, w.P, kmax, precision=args.precision, lb_items=args.lb_items,
+                      handoff_tiles=args.handoff_tiles)
     build_s = time.perf_counter() - t0
     st0 = idx.stats()
     print(f"[bench] index built in {build_s:.2f} s", file=sys.stderr, flush=True)
