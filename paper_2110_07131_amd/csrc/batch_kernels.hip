@@ -762,7 +762,7 @@ template <int NV, bool GROUP>
 __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   const int64_t B = blockIdx.x;
   int nch = 0, nusers = TILE;
-  const int32_t* glist = bv.sg_users + (int64_t)(bv.sg_level & 1) * ix.n_pad;  // group's input
+  const int32_t* glist = bv.sg_sorted;  // group's input: the current list ordered by depth
   int32_t* hlist = bv.sg_users + (int64_t)(GROUP ? (bv.sg_level & 1) ^ 1 : 0) * ix.n_pad;  // handed over
   int32_t* hcount = bv.sg_count + (GROUP ? (bv.sg_level & 1) ^ 1 : 0);
   if (GROUP) {
@@ -1293,6 +1293,19 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
         const int64_t u = urow(uo);
         hlist[atomicAdd(hcount, 1)] = (int32_t)u;
         if (bv.ctr) atomicAdd(&bv.ctr[C_HANDOFF], 1ull);
+        // depth key: the tile of the first item past the Corollary 1 limit
+        // of the user's deepest open pair (smallest lower bound), so that a
+        // group pass takes users of similar depth together
+        float lmin = INFINITY;
+        for (int p = 0; p < kUserPairs; ++p)
+          if ((rem >> p) & 1u) lmin = fminf(lmin, plo[p]);
+        int a = Cov[uo], b2 = (int)ix.m;
+        while (a < b2) {
+          const int mid = (a + b2) >> 1;
+          if (csut * ix.normP[mid] <= lmin) b2 = mid;
+          else a = mid + 1;
+        }
+        bv.sg_key[u] = a / TILE;
         if (!GROUP) {
           const int np = min(npu[uo], kUserPairs);
           bv.st_np[u] = np;
@@ -1360,6 +1373,37 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
       if (c_f64) atomicAdd(&bv.ctr[C_RCHK], c_f64);
       if (c_scan) atomicAdd(&bv.ctr[C_SCAN], c_scan);
     }
+  }
+}
+
+// The list of handed-over users ordered by their depth key (64 buckets over
+// the item tiles; order within a bucket arbitrary): one workgroup, counting
+// sort.
+__global__ void __launch_bounds__(1024) k_bsgsort(const int32_t* __restrict__ in,
+                                                  const int32_t* __restrict__ count,
+                                                  const int32_t* __restrict__ key,
+                                                  int32_t* __restrict__ out, int32_t mB) {
+  __shared__ int hist[64];
+  const int t = threadIdx.x;
+  const int n = *count;
+  if (t < 64) hist[t] = 0;
+  __syncthreads();
+  const int64_t span = (int64_t)mB + 1;
+  auto bucket = [&](int32_t u) { return (int)min((int64_t)63, (int64_t)key[u] * 64 / span); };
+  for (int i = t; i < n; i += 1024) atomicAdd(&hist[bucket(in[i])], 1);
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int b = 0; b < 64; ++b) {
+      const int c = hist[b];
+      hist[b] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += 1024) {
+    const int32_t u = in[i];
+    out[atomicAdd(&hist[bucket(u)], 1)] = u;
   }
 }
 
@@ -1619,6 +1663,8 @@ static void bscan_nv(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
     // the list this pass hands over to starts empty (the first is cleared with the chunk)
     if (lev > 0 && !g.sg_last)
       hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, g.sg_count + ((lev & 1) ^ 1), (int64_t)1, 0);
+    hipLaunchKernelGGL(k_bsgsort, dim3(1), dim3(1024), 0, s, g.sg_users + (int64_t)(lev & 1) * ix.n_pad,
+                       g.sg_count + (lev & 1), g.sg_key, g.sg_sorted, ix.mB);
     hipLaunchKernelGGL((k_bscan<NV, true>), dim3(ix.nB), dim3(256), lds, s, ix, g);
   }
   hipLaunchKernelGGL(k_bdecide, dim3(ix.nB), dim3(256), 0, s, ix, bv);

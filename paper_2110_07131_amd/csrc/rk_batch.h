@@ -58,6 +58,8 @@ struct BatchView {
   int32_t sg_level;             // group pass: reads list sg_level & 1, hands over to the other
   int32_t sg_last;              // group pass: 1 = the last, scans to the end
   int32_t* sg_block;            // [nB]
+  int32_t* sg_key;              // [n_pad] item tile of the deepest Corollary 1 limit of a handed user's open pairs
+  int32_t* sg_sorted;           // [n_pad] the current list ordered by that key (the group pass reads it)
   int32_t* st_np;               // [n_pad]
   int32_t* st_pk;               // [n_pad][kUserPairs]
   float* st_plo;                // [n_pad][kUserPairs]

@@ -108,7 +108,7 @@ struct rk_index {
     float* gl_v = nullptr;
     // users handed to the grouped pass and their pair slots
     int32_t *sg_count = nullptr, *sg_users = nullptr, *sg_block = nullptr, *st_np = nullptr,
-            *st_pk = nullptr;
+            *st_pk = nullptr, *sg_key = nullptr, *sg_sorted = nullptr;
     float *st_plo = nullptr, *st_ph = nullptr;
     int32_t chunk_cap = 0, maxc = 0;
     uint32_t* bits = nullptr;
@@ -532,7 +532,7 @@ BatchSizes batch_sizes(const rk_index* h, int32_t chunk) {
     b += std::max<int64_t>(pc, 1) * 4 + std::max<int64_t>(z.chunk_cap, 1) * 4 + 4 +
          std::max<int64_t>(ix.nB, 1) * 4 * (1 + z.maxc) +
          std::max<int64_t>(ix.n_pad, 1) * (8 * (int64_t)bscan_list_len(ix.kmax) + 4) + 4 +
-         std::max<int64_t>(ix.nB, 1) * 4 + std::max<int64_t>(ix.n_pad, 1) * (12 + 12 * kUserPairs) + 4;
+         std::max<int64_t>(ix.nB, 1) * 4 + std::max<int64_t>(ix.n_pad, 1) * (20 + 12 * kUserPairs) + 4;
   z.bytes = b;
   return z;
 }
@@ -559,10 +559,11 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
                   (void*)b.pair_st, (void*)b.cfill, (void*)b.nchunks, (void*)b.bcnt,
                   (void*)b.bchunks, (void*)b.gl_v, (void*)b.gl_i, (void*)b.gdone,
                   (void*)b.sg_count, (void*)b.sg_users, (void*)b.sg_block, (void*)b.st_np,
-                  (void*)b.st_pk, (void*)b.st_plo, (void*)b.st_ph})
+                  (void*)b.st_pk, (void*)b.st_plo, (void*)b.st_ph, (void*)b.sg_key,
+                  (void*)b.sg_sorted})
     if (p) h->dfree(p);
   b.pair_st = b.cfill = b.nchunks = b.bcnt = b.bchunks = b.gl_i = b.gdone = nullptr;
-  b.sg_count = b.sg_users = b.sg_block = b.st_np = b.st_pk = nullptr;
+  b.sg_count = b.sg_users = b.sg_block = b.st_np = b.st_pk = b.sg_key = b.sg_sorted = nullptr;
   b.gl_v = b.st_plo = b.st_ph = nullptr;
   const DevIndex& ix = h->ix;
   const BatchSizes z = batch_sizes(h, chunk);
@@ -603,6 +604,8 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
     HIPTRY(h->dalloc(&b.st_pk, np1 * kUserPairs));
     HIPTRY(h->dalloc(&b.st_plo, np1 * kUserPairs));
     HIPTRY(h->dalloc(&b.st_ph, np1 * kUserPairs));
+    HIPTRY(h->dalloc(&b.sg_key, np1));
+    HIPTRY(h->dalloc(&b.sg_sorted, np1));
   }
   HIPTRY(hipMemsetAsync(b.bits, 0, (size_t)chunk * std::max<int64_t>(W, 1) * 4, h->stream));
   HIPTRY(hipMemsetAsync(b.counts, 0, (size_t)chunk * 8, h->stream));
@@ -672,6 +675,7 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
     bv.gl_v = b.gl_v; bv.gl_i = b.gl_i; bv.gdone = b.gdone;
     bv.sg_count = b.sg_count; bv.sg_users = b.sg_users; bv.sg_block = b.sg_block;
     bv.st_np = b.st_np; bv.st_pk = b.st_pk; bv.st_plo = b.st_plo; bv.st_ph = b.st_ph;
+    bv.sg_key = b.sg_key; bv.sg_sorted = b.sg_sorted;
     bv.carry_in = c0 > 0;
     bv.carry_out = c0 + nc < nq;
     if (c0 == 0 && bv.carry_out) launch_bscan_reset(ix, bv, s);  // the scan state is per call
