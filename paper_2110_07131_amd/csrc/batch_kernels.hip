@@ -647,8 +647,8 @@ __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView b
 constexpr int kShortTiles = 4;
 constexpr int kFlagCap = 1024;  // flagged pairs listed in LDS per block
 constexpr int kHandoff = 24;    // at most this many users of a block still scanning: hand them over
-constexpr int kGroupHandoff = 24;  // the same for a group pass (but the last)
-constexpr int kGroupLevels = 3;    // group passes (thresholds and depth measured on 1M users x 100k items)
+constexpr int kGroupHandoff = 12;  // the same for a group pass (but the last)
+constexpr int kGroupLevels = 2;    // group passes (thresholds and depth measured on 1M users x 100k items)
 // ... and only with more than ix.handoff_tiles item tiles left (512 unless
 // the index options say otherwise: shorter tails cost less where they are
 // than the extra passes)
