@@ -69,6 +69,21 @@ def test_precision_config_full_size(prec):
     idx.free()
 
 
+def test_precision_config_full_size_short_prefix():
+    # the same workload with the paper's P' = 50: 3,000 queries in six query
+    # chunks, with lists carried across them, and the last users of most
+    # blocks handed to group passes (1,563 item tiles)
+    c = datagen.CONFIGS["precision"]
+    w = datagen.config_workload("precision")
+    ks = w.ks.astype(np.int32)
+    idx = Index.build(w.Q, w.P, c["k_max"], lb_items=50)
+    idx.set_counting(True)
+    off, ids = run_device_batch(idx, w.queries, ks, 512)
+    assert idx.stats()["scan_handoff"] > 0
+    check_sampled(w, w.queries, ks, c["k_max"], off, ids, 400, seed=4)
+    idx.free()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_batched_config_full_size(prec):
     # 500,000 users x 50,000 items, d = 200, sigma 0.8, 4,096 queries, k ~ U{1..50}
