@@ -645,6 +645,13 @@ __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView b
 // to group passes that continue 64 such users from any blocks at once.  The
 // lists and their coverage carry over to the next query chunk of the call.
 constexpr int kShortTiles = 4;
+// ALIAS mode: floats of the item-tile region (the tile, or the candidates,
+// their rows and the pair slots, whichever is larger)
+__host__ __device__ constexpr int bscan_tile_region(int d2) {
+  return d2 * TILE > TILE * TILE + TILE * TILE / 4 + 3 * TILE * kUserPairs
+             ? d2 * TILE
+             : TILE * TILE + TILE * TILE / 4 + 3 * TILE * kUserPairs;
+}
 constexpr int kFlagCap = 1024;  // flagged pairs listed in LDS per block
 constexpr int kHandoff = 24;    // at most this many users of a block still scanning: hand them over
 constexpr int kGroupHandoff = 12;  // the same for a group pass (but the last)
@@ -784,18 +791,26 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   // is usually not the item equal to q, so an undecided pair rarely needs
   // the float64 scan
   const int d = ix.d, d2 = d + (d & 1), K = bscan_list_len(ix.kmax), K4 = K / 4;
+  // ALIAS (65 <= d <= 128): the candidates, their rows and the pair slots
+  // share the item tile's region (written after a barrier once every wave
+  // has read the tile), and there is no list of flagged pairs, so that two
+  // workgroups fit a CU up to d ~ 110.
+  constexpr bool ALIAS = NV == 8;
   float* ubuf = (float*)lds_raw;        // [d2][64] users of the block
   float* pbuf = ubuf + d2 * TILE;       // [d2][64] current item tile
-  float* cand = pbuf + d2 * TILE;       // [64][64] candidates of the tile per user
-  float* topk = cand + TILE * TILE;     // [64][K] list values (sorted after each pass)
+  float* pend = pbuf + (ALIAS ? bscan_tile_region(d2) : d2 * TILE);
+  float* cand = ALIAS ? pbuf : pend;    // [64][64] candidates of the tile per user
+  float* topk = ALIAS ? pend : cand + TILE * TILE;  // [64][K] list values (sorted after each pass)
   int32_t* topi = (int32_t*)(topk + TILE * K);  // [64][K] their item ids (-1: none)
   float* thr = (float*)(topi + TILE * K);       // [64] smallest list value
   int* ccnt = (int*)(thr + TILE);       // [64] candidates per user
   int* open = ccnt + TILE;              // [64] 1 while a flagged pair of the user needs items
   int* Cov = open + TILE;               // [64] items covered by the user's list
-  uint8_t* crow = (uint8_t*)(Cov + TILE);  // [64][64] candidate rows within the tile
+  // [64][64] candidate rows within the tile
+  uint8_t* crow = ALIAS ? (uint8_t*)(pbuf + TILE * TILE) : (uint8_t*)(Cov + TILE);
   __shared__ int nflag, more_w[4];
-  __shared__ int32_t flist[kFlagCap];  // slots of the flagged pairs
+  constexpr int flist_cap = ALIAS ? 0 : kFlagCap;
+  __shared__ int32_t flist[ALIAS ? 1 : kFlagCap];  // slots of the flagged pairs
   // Long pass, per user: kUserPairs slots of flagged pairs (largest k,
   // smallest lower and largest upper bound of f(q,u), as ordered integer
   // keys); the last slot holds the extremes over the user's remaining pairs,
@@ -805,7 +820,10 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   // bound); a user stops when all its slots have.  Also the user's error
   // bound of a product.
   __shared__ int npu[TILE];
-  __shared__ int pk_s[TILE * kUserPairs], plo_s[TILE * kUserPairs], phi_s[TILE * kUserPairs];
+  __shared__ int slots_st[ALIAS ? 1 : 3 * TILE * kUserPairs];
+  int* pk_s = ALIAS ? (int*)(pbuf + TILE * TILE + TILE * TILE / 4) : slots_st;
+  int* plo_s = pk_s + TILE * kUserPairs;
+  int* phi_s = plo_s + TILE * kUserPairs;
   __shared__ float eu[TILE];
   const int32_t* clist = bv.bchunks + B * bv.maxc;
   // sorted index of the user of column c (c < nusers)
@@ -840,11 +858,6 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
       ccnt[t] = 0;
       open[t] = 0;
       npu[t] = 0;
-    }
-    for (int i = t; i < TILE * kUserPairs; i += 256) {
-      pk_s[i] = 0;
-      plo_s[i] = INT_MAX;
-      phi_s[i] = INT_MIN;
     }
     if (t == 0) nflag = 0;
   }
@@ -890,11 +903,17 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   // quad then puts each candidate in place of the list's minimum.  The next
   // tile is prefetched into registers.
   u32x4 pf[NV];
+  // the next tile into pbuf (ALIAS: also its zero row for odd d, which the
+  // candidates overwrote)
+  auto store_tile = [&]() {
+    store_item_tile(pbuf, d, t, pf);
+    if (ALIAS && (d & 1) && t < TILE) pbuf[d * TILE + t] = 0.f;
+  };
   auto scan_tiles = [&](int I0, int I1, bool all_users) {
     if (I0 >= I1) return;
     load_item_tile(ix, I0, t, pf);
     __syncthreads();
-    store_item_tile(pbuf, d, t, pf);
+    store_tile();
     if (I0 + 1 < I1) load_item_tile(ix, I0 + 1, t, pf);
     for (int I = I0; I < I1; ++I) {
       __syncthreads();  // pbuf holds tile I; candidate lists are empty
@@ -916,13 +935,18 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
       // tile on the vector ALU, one item per lane, instead of MFMA quarters.
       unsigned long long am = 0;
       if (!all_users) am = __ballot(open[lane] && I * TILE >= Cov[lane]);
-      if (!all_users && __popcll(am) <= 8) {
+      const bool sparse = !all_users && __popcll(am) <= 8;
+      const int64_t left = ix.m - (int64_t)I * TILE;  // items of this tile that exist
+      int u0 = -1, u1 = -1;
+      float va = 0.f, vb = 0.f;
+      f32x16 acc = {};
+      bool dense = false;
+      if (sparse) {
         unsigned long long mk = am;
         for (int i = 0; i < wave; ++i) mk &= mk - 1;
-        const int u0 = mk ? __ffsll(mk) - 1 : -1;
+        u0 = mk ? __ffsll(mk) - 1 : -1;
         for (int i = 0; i < 4 && mk; ++i) mk &= mk - 1;
-        const int u1 = mk ? __ffsll(mk) - 1 : -1;
-        const int64_t left = ix.m - (int64_t)I * TILE;
+        u1 = mk ? __ffsll(mk) - 1 : -1;
         const float* pc = pbuf + lane;
         if (u0 >= 0 && u1 < 0) {
           float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
@@ -935,12 +959,7 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
             a3 = fmaf(pc[(k + 3) * TILE], x0[(k + 3) * TILE], a3);
           }
           for (; k < d; ++k) a0 = fmaf(pc[k * TILE], x0[k * TILE], a0);
-          const float v = (a0 + a1) + (a2 + a3);
-          if (lane < left && v > thr[u0]) {
-            const int at = atomicAdd(&ccnt[u0], 1);
-            cand[u0 * TILE + at] = v;
-            crow[u0 * TILE + at] = (uint8_t)lane;
-          }
+          va = (a0 + a1) + (a2 + a3);
         } else if (u1 >= 0) {
           float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
           const float* x0 = ubuf + u0;
@@ -957,20 +976,12 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
             a0 = fmaf(pc[k * TILE], x0[k * TILE], a0);
             b0 = fmaf(pc[k * TILE], x1[k * TILE], b0);
           }
-          const float va = a0 + a1, vb = b0 + b1;
-          if (lane < left && va > thr[u0]) {
-            const int at = atomicAdd(&ccnt[u0], 1);
-            cand[u0 * TILE + at] = va;
-            crow[u0 * TILE + at] = (uint8_t)lane;
-          }
-          if (lane < left && vb > thr[u1]) {
-            const int at = atomicAdd(&ccnt[u1], 1);
-            cand[u1 * TILE + at] = vb;
-            crow[u1 * TILE + at] = (uint8_t)lane;
-          }
+          va = a0 + a1;
+          vb = b0 + b1;
         }
       } else if (__ballot(act)) {
-        f32x16 acc = {}, acc2 = {};
+        dense = true;
+        f32x16 acc2 = {};
         const float* pf_ = pbuf + ih * 32 + col + half * TILE;
         const float* uf = ubuf + uh * 32 + col + half * TILE;
         const int nsteps = d2 / 2;
@@ -990,23 +1001,35 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
         for (; ks < nsteps; ++ks)
           acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pf_[2 * ks * TILE], uf[2 * ks * TILE], acc, 0, 0, 0);
         acc += acc2;
-        if (act) {
-          const int64_t left = ix.m - (int64_t)I * TILE;  // items of this tile that exist
-          const float th = thr[ul];
+      }
+      if (ALIAS) __syncthreads();  // every wave has read the tile: its region takes the candidates
+      // products above the user's list minimum become candidates
+      if (sparse) {
+        if (u0 >= 0 && lane < left && va > thr[u0]) {
+          const int at = atomicAdd(&ccnt[u0], 1);
+          cand[u0 * TILE + at] = va;
+          crow[u0 * TILE + at] = (uint8_t)lane;
+        }
+        if (u1 >= 0 && lane < left && vb > thr[u1]) {
+          const int at = atomicAdd(&ccnt[u1], 1);
+          cand[u1 * TILE + at] = vb;
+          crow[u1 * TILE + at] = (uint8_t)lane;
+        }
+      } else if (dense && act) {
+        const float th = thr[ul];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int row = quarter_row(ih, half, r);
-            if (row < left && acc[r] > th) {
-              const int at = atomicAdd(&ccnt[ul], 1);
-              cand[ul * TILE + at] = acc[r];
-              crow[ul * TILE + at] = (uint8_t)row;
-            }
+        for (int r = 0; r < 16; ++r) {
+          const int row = quarter_row(ih, half, r);
+          if (row < left && acc[r] > th) {
+            const int at = atomicAdd(&ccnt[ul], 1);
+            cand[ul * TILE + at] = acc[r];
+            crow[ul * TILE + at] = (uint8_t)row;
           }
         }
       }
-      __syncthreads();  // candidates complete; pbuf free
-      if (I + 1 < I1) {
-        store_item_tile(pbuf, d, t, pf);
+      __syncthreads();  // candidates complete; pbuf free (unless ALIAS: it holds them)
+      if (!ALIAS && I + 1 < I1) {
+        store_tile();
         if (I + 2 < I1) load_item_tile(ix, I + 2, t, pf);
       }
       {
@@ -1053,6 +1076,13 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
         if (!all_users) {
           const unsigned long long still = __ballot(rem != 0u);
           if (lane == 0) more_w[wave] = still != 0ull;
+        }
+      }
+      if (ALIAS) {
+        __syncthreads();  // candidates consumed: the region takes the next tile
+        if (I + 1 < I1) {
+          store_tile();
+          if (I + 2 < I1) load_item_tile(ix, I + 2, t, pf);
         }
       }
     }
@@ -1109,6 +1139,13 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   if (sub == 0) thr[uo] = gmn;  // read after the next barrier
   const float e0 = ix.eps_rel32 * ix.normP[0];  // times |u|, plus eps_abs: any product's bound
   if (!GROUP) scan_tiles(0, nshort, true);
+  // pair slots (after the short pass: in ALIAS mode they share the tile region)
+  for (int i = t; i < TILE * kUserPairs; i += 256) {
+    pk_s[i] = 0;
+    plo_s[i] = INT_MAX;
+    phi_s[i] = INT_MIN;
+  }
+  __syncthreads();
 
   // f(q,u) in [lo, hi]: float32 bounds (recomputed from the float32 rows in
   // bf16 mode, where the filter's product is a bf16 one).
@@ -1189,7 +1226,7 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
       bv.pair_st[slot[g]] = cls == 2;
       if (cls == 2) {
         const int at = atomicAdd(&nflag, 1);
-        if (at < kFlagCap) flist[at] = (int32_t)slot[g];
+        if (at < flist_cap) flist[at] = (int32_t)slot[g];
         ++c_long;
       }
       bool yes = cls == 1;
@@ -1332,7 +1369,7 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
         }
       }
       if (t < nusers) bv.gdone[urow(t)] = Cov[t];
-    } else if (nfl <= kFlagCap) {
+    } else if (nfl <= flist_cap) {
       for (int i = t; i < nfl; i += 256) decide_flagged(flist[i]);
     } else {  // more than the list holds: find them by their flags
       for (int ci = 0; ci < nch; ++ci) {
@@ -1634,6 +1671,10 @@ void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
 
 size_t bscan_lds_bytes(const DevIndex& ix) {
   const size_t d2 = (size_t)(ix.d + (ix.d & 1));
+  const int per_thread = (ix.d * (TILE / 4) + 255) / 256;  // the kernel's NV: ALIAS when 8
+  if (per_thread > 4 && per_thread <= 8)
+    return (d2 * TILE + bscan_tile_region((int)d2) + 2 * (size_t)TILE * bscan_list_len(ix.kmax) +
+            4 * TILE) * 4;
   return (2 * d2 * TILE + TILE * TILE + 2 * (size_t)TILE * bscan_list_len(ix.kmax) + 4 * TILE) * 4 +
          TILE * TILE;
 }

@@ -339,6 +339,22 @@ def test_grouped_scan_handoff_on_short_catalogs_several_chunks():
     idx.free()
 
 
+@pytest.mark.parametrize("d,prec,handoff", [(100, "fp32", 0), (99, "fp32", 1), (100, "bf16", 1),
+                                              (66, "fp32", 1)])
+def test_grouped_scan_shared_tile_region(d, prec, handoff):
+    # 65 <= d <= 128: the scan's candidates and pair slots share the item
+    # tile's region (odd d: its zero row is restored after every tile)
+    w = datagen.workload(700, 1500, d, 0.6, 40, seed=d)
+    rng = np.random.default_rng(d)
+    ks = rng.integers(1, 9, len(w.qidx)).astype(np.int32)
+    idx = Index.build(w.Q, w.P, 8, lb_items=10, precision=prec, handoff_tiles=handoff)
+    idx.set_counting(True)
+    off, ids = idx.reverse_kmips_batch(w.queries, ks)
+    check_csr(w.Q, w.P, w.queries, ks, off, ids)
+    assert idx.stats()["scan_long"] > 0
+    idx.free()
+
+
 # --- limits: largest k_max, widest d ----------------------------------------
 
 @pytest.mark.parametrize("lb,prec", [(0, "fp32"), (130, "fp32"), (130, "bf16")])
