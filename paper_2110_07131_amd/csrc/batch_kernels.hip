@@ -765,7 +765,7 @@ __device__ __forceinline__ int quad_sum(int v) {
 // (from any blocks), the long pass only, continued from their lists; it
 // hands over its last kGroupHandoff users in turn, but in the last group
 // pass.  Their pairs are decided by k_bdecide.
-template <int NV, bool GROUP>
+template <int NV, bool GROUP, bool ALIAS>
 __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   const int64_t B = blockIdx.x;
   int nch = 0, nusers = TILE;
@@ -791,11 +791,11 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   // is usually not the item equal to q, so an undecided pair rarely needs
   // the float64 scan
   const int d = ix.d, d2 = d + (d & 1), K = bscan_list_len(ix.kmax), K4 = K / 4;
-  // ALIAS (65 <= d <= 128): the candidates, their rows and the pair slots
-  // share the item tile's region (written after a barrier once every wave
-  // has read the tile), and there is no list of flagged pairs, so that two
-  // workgroups fit a CU up to d ~ 110.
-  constexpr bool ALIAS = NV == 8;
+  // ALIAS (65 <= d <= 128, and wider tiles whose separate buffers would not
+  // fit): the candidates, their rows and the pair slots share the item
+  // tile's region (written after a barrier once every wave has read the
+  // tile), and there is no list of flagged pairs, so that two workgroups fit
+  // a CU up to d ~ 110.
   float* ubuf = (float*)lds_raw;        // [d2][64] users of the block
   float* pbuf = ubuf + d2 * TILE;       // [d2][64] current item tile
   float* pend = pbuf + (ALIAS ? bscan_tile_region(d2) : d2 * TILE);
@@ -1669,32 +1669,50 @@ void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
   else bfilter_prec<false>(ix, bv, lds, s);
 }
 
-size_t bscan_lds_bytes(const DevIndex& ix) {
+static size_t bscan_lds_mode(const DevIndex& ix, bool alias) {
   const size_t d2 = (size_t)(ix.d + (ix.d & 1));
-  const int per_thread = (ix.d * (TILE / 4) + 255) / 256;  // the kernel's NV: ALIAS when 8
-  if (per_thread > 4 && per_thread <= 8)
+  if (alias)
     return (d2 * TILE + bscan_tile_region((int)d2) + 2 * (size_t)TILE * bscan_list_len(ix.kmax) +
             4 * TILE) * 4;
   return (2 * d2 * TILE + TILE * TILE + 2 * (size_t)TILE * bscan_list_len(ix.kmax) + 4 * TILE) * 4 +
          TILE * TILE;
 }
 
-size_t bscan_static_lds() {
+static size_t bscan_static_mode(bool alias) {
   hipFuncAttributes a{};
-  if (hipFuncGetAttributes(&a, (const void*)k_bscan<2, false>) != hipSuccess) return 16384;
+  const void* f = alias ? (const void*)k_bscan<16, false, true> : (const void*)k_bscan<2, false, false>;
+  if (hipFuncGetAttributes(&a, f) != hipSuccess) return 16384;
   return a.sharedSizeBytes;
 }
 
-template <int NV>
+constexpr size_t kBscanMaxLds = 160 * 1024;
+
+// The shared tile region: tiles of 65..128 coordinates (two workgroups per
+// CU), and wider ones whose separate buffers would not fit.
+static bool bscan_alias(const DevIndex& ix) {
+  const int per_thread = (ix.d * (TILE / 4) + 255) / 256;  // the kernel's NV
+  if (per_thread <= 4) return false;
+  if (per_thread <= 8) return true;
+  return bscan_lds_mode(ix, false) + bscan_static_mode(false) > kBscanMaxLds;
+}
+
+size_t bscan_lds_bytes(const DevIndex& ix) { return bscan_lds_mode(ix, bscan_alias(ix)); }
+
+bool bscan_fits(const DevIndex& ix) {
+  const bool alias = bscan_alias(ix);
+  return bscan_lds_mode(ix, alias) + bscan_static_mode(alias) <= kBscanMaxLds;
+}
+
+template <int NV, bool ALIAS>
 static void bscan_nv(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
-  const size_t lds = bscan_lds_bytes(ix);
+  const size_t lds = bscan_lds_mode(ix, ALIAS);
   if (lds > 65536) {
-    (void)hipFuncSetAttribute((const void*)k_bscan<NV, false>,
+    (void)hipFuncSetAttribute((const void*)k_bscan<NV, false, ALIAS>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)k_bscan<NV, true>,
+    (void)hipFuncSetAttribute((const void*)k_bscan<NV, true, ALIAS>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
-  hipLaunchKernelGGL((k_bscan<NV, false>), dim3(ix.nB), dim3(256), lds, s, ix, bv);
+  hipLaunchKernelGGL((k_bscan<NV, false, ALIAS>), dim3(ix.nB), dim3(256), lds, s, ix, bv);
   // the handed-over users, 64 per workgroup (at most nB groups; the rest
   // exit), in passes over alternating lists
   for (int lev = 0; lev < kGroupLevels; ++lev) {
@@ -1706,7 +1724,7 @@ static void bscan_nv(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
       hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, g.sg_count + ((lev & 1) ^ 1), (int64_t)1, 0);
     hipLaunchKernelGGL(k_bsgsort, dim3(1), dim3(1024), 0, s, g.sg_users + (int64_t)(lev & 1) * ix.n_pad,
                        g.sg_count + (lev & 1), g.sg_key, g.sg_sorted, ix.mB);
-    hipLaunchKernelGGL((k_bscan<NV, true>), dim3(ix.nB), dim3(256), lds, s, ix, g);
+    hipLaunchKernelGGL((k_bscan<NV, true, ALIAS>), dim3(ix.nB), dim3(256), lds, s, ix, g);
   }
   hipLaunchKernelGGL(k_bdecide, dim3(ix.nB), dim3(256), 0, s, ix, bv);
 }
@@ -1718,10 +1736,11 @@ void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
     return;
   }
   const int per_thread = (ix.d * (TILE / 4) + 255) / 256;  // 16-byte vectors of an item tile
-  if (per_thread <= 2) bscan_nv<2>(ix, bv, s);
-  else if (per_thread <= 4) bscan_nv<4>(ix, bv, s);
-  else if (per_thread <= 8) bscan_nv<8>(ix, bv, s);
-  else bscan_nv<16>(ix, bv, s);
+  if (per_thread <= 2) bscan_nv<2, false>(ix, bv, s);
+  else if (per_thread <= 4) bscan_nv<4, false>(ix, bv, s);
+  else if (per_thread <= 8) bscan_nv<8, true>(ix, bv, s);
+  else if (bscan_alias(ix)) bscan_nv<16, true>(ix, bv, s);
+  else bscan_nv<16, false>(ix, bv, s);
 }
 
 void launch_bassemble(const BatchView& bv, int32_t nq, const int64_t* base, int64_t* offs,

@@ -75,7 +75,8 @@ void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 // Dynamic LDS of the grouped linear scan (bounded table).
 size_t bscan_lds_bytes(const DevIndex& ix);
-size_t bscan_static_lds();  // its static LDS (the same for every instantiation)
+// whether the scan's workgroup (dynamic and static LDS) fits a CU
+bool bscan_fits(const DevIndex& ix);
 // Bounded table: the carried scan state starts empty for a batch call.
 void launch_bscan_reset(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 // offs[0] must hold the chunk's first offset; writes offs[1..nq] and ids.

@@ -646,7 +646,7 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
   if (nq == 0) return RK_OK;
   const size_t tile_bytes = ix.bf16 ? (size_t)ix.d16 * TILE * 2 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
   if (bfilter_lds_bytes(ix) > kMaxLds || tile_bytes > bfilter_max_tile_bytes() ||
-      (!ix.exact && bscan_lds_bytes(ix) + bscan_static_lds() > kMaxLds)) {
+      (!ix.exact && !bscan_fits(ix))) {
     // too wide for the block-resident batched filter: one query at a time
     for (int64_t i = 0; i < nq; ++i) {
       rk_status st = enqueue_query(h, qs_dev + i * ix.d, ks[i], ids, cap, offs + i, offs + i + 1,

@@ -355,6 +355,22 @@ def test_grouped_scan_shared_tile_region(d, prec, handoff):
     idx.free()
 
 
+@pytest.mark.parametrize("d", [200, 255])
+def test_grouped_scan_shared_region_wide_tiles(d):
+    # k_max = 50 at d = 200 or 255: separate candidate buffers would not fit
+    # the CU's LDS (the batch would go one query at a time); with the shared
+    # region the grouped scan runs
+    w = datagen.workload(500, 1200, d, 0.8, 30, seed=d)
+    rng = np.random.default_rng(d)
+    ks = rng.integers(1, 51, len(w.qidx)).astype(np.int32)
+    idx = Index.build(w.Q, w.P, 50, lb_items=60, handoff_tiles=1)
+    idx.set_counting(True)
+    off, ids = idx.reverse_kmips_batch(w.queries, ks)
+    check_csr(w.Q, w.P, w.queries, ks, off, ids)
+    assert idx.stats()["scan_long"] > 0
+    idx.free()
+
+
 # --- limits: largest k_max, widest d ----------------------------------------
 
 @pytest.mark.parametrize("lb,prec", [(0, "fp32"), (130, "fp32"), (130, "bf16")])
