@@ -354,8 +354,9 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   }
 
   while (T < nT) {
-    // bf16: the next live tile streams into the other buffer (read last in
-    // the previous step, which every wave has finished) while this one is used
+    // small bf16 tiles: the next live tile streams into the other buffer
+    // (read last in the previous step, which every wave has finished) while
+    // this one is used
     if (LDSD && Tn < nT)
       issue_tile(qsrc, bv, Tn, tile_bytes, lane, wave, qbuf2[slot ^ 1], meta_n2 + (slot ^ 1) * TILE,
                  meta_k2 + (slot ^ 1) * TILE);
@@ -553,8 +554,8 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
 
     }  // hmask
 
-    // ---- next tile: bf16 landed in the other buffer; float32 from the
-    // prefetch registers into the one buffer
+    // ---- next tile: small bf16 tiles landed in the other buffer; others
+    // from the prefetch registers into the one buffer
     if constexpr (LDSD) {
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
