@@ -113,7 +113,7 @@ __global__ void k_btile(const float* __restrict__ qs, const int32_t* __restrict_
                         int32_t nq, int32_t nq_pad, int32_t d, int32_t d16, int64_t m,
                         float* __restrict__ qt, uint16_t* __restrict__ qb,
                         float* __restrict__ qn_s, int32_t* __restrict__ k_s,
-                        uint8_t* __restrict__ all) {
+                        int32_t* __restrict__ kofs_s, uint8_t* __restrict__ all) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
   if (r >= nq_pad) return;
   const bool valid = r < nq;
@@ -132,6 +132,7 @@ __global__ void k_btile(const float* __restrict__ qs, const int32_t* __restrict_
     const int32_t k = valid ? ks[src] : 0;
     qn_s[r] = valid ? qn[src] : 0.0f;
     k_s[r] = k > m ? 0 : k;
+    kofs_s[r] = (k > m || k < 1 ? 0 : k - 1) * TILE;
     if (valid) all[src] = k > m ? 1 : 0;
   }
 }
@@ -190,7 +191,7 @@ __device__ __forceinline__ void stage_tile(const u32x4* __restrict__ qsrc, const
     if (i < tile_vecs) pf[v] = src[i];
   }
   if (t < TILE) pf_n = bv.qn_s[(int64_t)T * TILE + t];
-  else if (t < 2 * TILE) pf_k = bv.k_s[(int64_t)T * TILE + t - TILE];
+  else if (t < 2 * TILE) pf_k = bv.kofs_s[(int64_t)T * TILE + t - TILE];
 }
 
 template <int NV>
@@ -212,7 +213,7 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 // Query tile T and its metadata straight from global memory into LDS
 // (global_load_lds: lane l of a wave writes 16 bytes at the wave's LDS base +
 // 16 l, so one instruction moves 1 KiB): wave w moves the 1 KiB chunks w,
-// w+4, ...; waves 0 and 1 move the 64 norms and k values.  The data is there
+// w+4, ...; waves 0 and 1 move the 64 norms and k rows.  The data is there
 // once the issuing wave has waited for its vector memory operations.
 __device__ __forceinline__ void issue_tile(const unsigned char* __restrict__ qsrc, const BatchView& bv,
                                            int T, int tile_bytes, int lane, int wave,
@@ -227,7 +228,7 @@ __device__ __forceinline__ void issue_tile(const unsigned char* __restrict__ qsr
     __builtin_amdgcn_global_load_lds((const void*)(bv.qn_s + (int64_t)T * TILE + lane),
                                      (lds_void_t*)mn_dst, 4, 0, 0);
   else if (wave == 1)
-    __builtin_amdgcn_global_load_lds((const void*)(bv.k_s + (int64_t)T * TILE + lane),
+    __builtin_amdgcn_global_load_lds((const void*)(bv.kofs_s + (int64_t)T * TILE + lane),
                                      (lds_void_t*)mk_dst, 4, 0, 0);
 }
 
@@ -267,7 +268,7 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   if (LDSD) p += (tile_bytes + 15) / 16 * 16;
   float* meta_n2 = (float*)p;    // [2][64] norms of the tile's queries
   p += 2 * TILE * 4;
-  int32_t* meta_k2 = (int32_t*)p;  // [2][64] their k
+  int32_t* meta_k2 = (int32_t*)p;  // [2][64] their k's rows in the (k, user) tables
   p += 2 * TILE * 4;
   unsigned long long* masks = (unsigned long long*)p;
   p += (kBatchChunkMax / TILE) * 8;
@@ -427,7 +428,7 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
       for (int i = 0; i < 4; ++i) {
         const int r = g * 4 + i;
         const float ev = fmaf(a_u, nqs[i], ix.eps_abs);
-        const float L = Ll[(max(kks[i], 1) - 1) * TILE + ucol];
+        const float L = Ll[kks[i] + ucol];
         rest |= (uint32_t)!(acc[r] + ev < L) << r;
       }
     }
@@ -445,7 +446,7 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
         for (int i = 0; i < 4; ++i) {
           const int r = g * 4 + i;
           const float ev = fmaf(a_u, nqs[i], ix.eps_abs);
-          const float Y = Yl[(max(kks[i], 1) - 1) * TILE + ucol];
+          const float Y = Yl[kks[i] + ucol];
           yes |= (uint32_t)(acc[r] - ev >= Y) << r;
         }
       }
@@ -1632,7 +1633,7 @@ void launch_bprep(const DevIndex& ix, const BatchView& bv, const int32_t* ks_dev
   dim3 blk(64, 4);
   hipLaunchKernelGGL(k_btile, dim3((bv.nq_pad + 3) / 4), blk, 0, s, bv.qs, ks_dev, bv.qn,
                      bv.perm, nq, bv.nq_pad, ix.d, ix.d16, ix.m, bv.qt, ix.bf16 ? bv.qb : nullptr,
-                     bv.qn_s, bv.k_s, bv.all);
+                     bv.qn_s, bv.k_s, bv.kofs_s, bv.all);
 }
 
 size_t bfilter_lds_bytes(const DevIndex& ix) {

@@ -19,6 +19,7 @@ struct BatchView {
   uint16_t* qb;                 // sorted query tiles, bf16 [T][G][64][8]
   float* qn_s;                  // [nq_pad] sorted norms
   int32_t* k_s;                 // [nq_pad] sorted k (0 = padding or no work)
+  int32_t* kofs_s;              // [nq_pad] 64 (max(k,1) - 1): the k's row of the filter's (k, user) tables
   int32_t nq_pad;
   uint32_t* bits;               // [nq][W] result bits by original user id
   int64_t W;                    // words per bitmap row

@@ -100,7 +100,7 @@ struct rk_index {
     int64_t pair_cap = 0;
     float *qn = nullptr, *qt = nullptr, *qn_s = nullptr, *pair_s = nullptr;
     uint16_t* qb = nullptr;
-    int32_t *perm = nullptr, *k_s = nullptr, *npairs = nullptr, *pair_u = nullptr,
+    int32_t *perm = nullptr, *k_s = nullptr, *kofs_s = nullptr, *npairs = nullptr, *pair_u = nullptr,
             *pair_j = nullptr, *ks_dev = nullptr;
     // bounded table: chunked pair slots, per-block chunk lists
     int32_t *pair_st = nullptr, *cfill = nullptr, *nchunks = nullptr, *bcnt = nullptr,
@@ -526,7 +526,7 @@ BatchSizes batch_sizes(const rk_index* h, int32_t chunk) {
   }
   z.pc = pc;
   const int64_t d2 = ix.d + (ix.d & 1);
-  int64_t b = chunk * 4 * 2 + cp * d2 * 4 + (ix.bf16 ? cp * ix.d16 * 2 : 0) + cp * 8 +
+  int64_t b = chunk * 4 * 2 + cp * d2 * 4 + (ix.bf16 ? cp * ix.d16 * 2 : 0) + cp * 12 +
               chunk * W * 4 + chunk * 8 + chunk + 4 + pc * 12 + chunk * 4;
   if (!ix.exact)
     b += std::max<int64_t>(pc, 1) * 4 + std::max<int64_t>(z.chunk_cap, 1) * 4 + 4 +
@@ -554,7 +554,8 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
   if (b.qcap >= chunk) return RK_OK;
   HIPTRY(hipStreamSynchronize(h->stream));
   for (void* p : {(void*)b.qn, (void*)b.qt, (void*)b.qn_s, (void*)b.pair_s, (void*)b.qb,
-                  (void*)b.perm, (void*)b.k_s, (void*)b.npairs, (void*)b.pair_u, (void*)b.pair_j,
+                  (void*)b.perm, (void*)b.k_s, (void*)b.kofs_s, (void*)b.npairs, (void*)b.pair_u,
+                  (void*)b.pair_j,
                   (void*)b.ks_dev, (void*)b.bits, (void*)b.counts, (void*)b.all,
                   (void*)b.pair_st, (void*)b.cfill, (void*)b.nchunks, (void*)b.bcnt,
                   (void*)b.bchunks, (void*)b.gl_v, (void*)b.gl_i, (void*)b.gdone,
@@ -576,6 +577,7 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
   if (ix.bf16) HIPTRY(h->dalloc(&b.qb, cp * ix.d16));
   HIPTRY(h->dalloc(&b.qn_s, cp));
   HIPTRY(h->dalloc(&b.k_s, cp));
+  HIPTRY(h->dalloc(&b.kofs_s, cp));
   HIPTRY(h->dalloc(&b.bits, (size_t)chunk * std::max<int64_t>(W, 1)));
   HIPTRY(h->dalloc(&b.counts, chunk));
   HIPTRY(h->dalloc(&b.all, chunk));
@@ -666,7 +668,7 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
     BatchView bv{};
     bv.qs = qs_dev + c0 * ix.d;
     bv.qn = b.qn; bv.perm = b.perm; bv.qt = b.qt; bv.qb = b.qb;
-    bv.qn_s = b.qn_s; bv.k_s = b.k_s; bv.nq_pad = (int32_t)round_up(nc, TILE);
+    bv.qn_s = b.qn_s; bv.k_s = b.k_s; bv.kofs_s = b.kofs_s; bv.nq_pad = (int32_t)round_up(nc, TILE);
     bv.bits = b.bits; bv.W = W; bv.counts = b.counts; bv.all = b.all; bv.n = ix.n;
     bv.npairs = b.npairs; bv.pair_cap = (int32_t)b.pair_cap;
     bv.pair_u = b.pair_u; bv.pair_j = b.pair_j; bv.pair_s = b.pair_s;
