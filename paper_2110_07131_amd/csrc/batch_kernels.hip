@@ -180,6 +180,12 @@ __device__ __forceinline__ int next_live(const unsigned long long* masks, int fr
 
 // Prefetch of query tile T (tile_vecs 16-byte vectors, thread t takes
 // t, t+256, ...) and its metadata into registers, and their store to LDS.
+// A tile of NV >= 4 vectors per thread has more than NV / 2 of them (the
+// launch picks the smallest NV that holds it), so the low half needs no bound
+// check.
+template <int NV>
+__device__ __forceinline__ constexpr bool lo_half(int v) { return NV >= 4 && v < NV / 2; }
+
 template <int NV>
 __device__ __forceinline__ void stage_tile(const u32x4* __restrict__ qsrc, const BatchView& bv,
                                            int T, int tile_vecs, int t, u32x4 (&pf)[NV],
@@ -188,7 +194,7 @@ __device__ __forceinline__ void stage_tile(const u32x4* __restrict__ qsrc, const
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int i = v * 256 + t;
-    if (i < tile_vecs) pf[v] = src[i];
+    if (lo_half<NV>(v) || i < tile_vecs) pf[v] = src[i];
   }
   if (t < TILE) pf_n = bv.qn_s[(int64_t)T * TILE + t];
   else if (t < 2 * TILE) pf_k = bv.kofs_s[(int64_t)T * TILE + t - TILE];
@@ -202,7 +208,7 @@ __device__ __forceinline__ void commit_tile(unsigned char* qbuf, float* meta_n, 
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int i = v * 256 + t;
-    if (i < tile_vecs) dst[i] = pf[v];
+    if (lo_half<NV>(v) || i < tile_vecs) dst[i] = pf[v];
   }
   if (t < TILE) meta_n[t] = pf_n;
   else if (t < 2 * TILE) meta_k[t - TILE] = pf_k;
@@ -232,12 +238,26 @@ __device__ __forceinline__ void issue_tile(const unsigned char* __restrict__ qsr
                                      (lds_void_t*)mk_dst, 4, 0, 0);
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave in registers (DPP): the
+// shifts by 1, 2, 4 and 8 lanes scan each row of 16 lanes (a lane with no
+// source lane adds 0), then the last lane of row 0 (of row 2) is added to row 1
+// (row 3), and that of row 1 to rows 2 and 3.
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 -> rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 -> rows 2, 3
+  return x;
+}
+
 __device__ __forceinline__ int quarter_row(int qhalf, int half, int r) {
   return qhalf * 32 + (r / 4) * 8 + half * 4 + (r % 4);
 }
 
-// Occupancy: float32 tiles of d <= 64 (NV <= 4) run 4 waves per SIMD (a
-// 32-byte spill, 2% faster measured); wider tiles keep their prefetch
+// Occupancy: float32 tiles of d <= 64 (NV <= 4) run 4 waves per SIMD
+// (within 128 registers, no spill); wider tiles keep their prefetch
 // registers and 2-3 waves.
 template <bool BF16, int NV>
 __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(DevIndex ix, BatchView bv) {
@@ -368,9 +388,9 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
     // this wave's query half may have no live query at all
     const uint32_t hmask = (uint32_t)(mask >> (qhalf * 32));
     if (hmask != 0u) {
-    // ---- scores of the quarter: S[query][user], 32 x 32 (two accumulators
-    // alternate over the k-steps and are summed at the end)
-    f32x16 acc = {}, acc2 = {};
+    // ---- scores of the quarter: S[query][user], 32 x 32, one accumulator
+    // (a second one alternating over the k-steps measured 1-4% slower)
+    f32x16 acc = {};
     if (!BF16) {
       const float* qf = (const float*)qbuf + qhalf * 32 + col + half * TILE;
       const float* uf = (const float*)ubuf + uh * 32 + col + half * TILE;
@@ -383,10 +403,8 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
           a[i] = qf[(2 * (ks + i)) * TILE];
           b[i] = uf[(2 * (ks + i)) * TILE];
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[0], acc, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b[1], acc2, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], b[2], acc, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], b[3], acc2, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[i], acc, 0, 0, 0);
       }
       for (; ks < nsteps; ++ks)
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(qf[2 * ks * TILE], uf[2 * ks * TILE], acc, 0, 0, 0);
@@ -399,12 +417,11 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
         const bf16x8 a0 = qv[2 * ks * TILE], b0 = uv[2 * ks * TILE];
         const bf16x8 a1 = qv[(2 * ks + 2) * TILE], b1 = uv[(2 * ks + 2) * TILE];
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc2, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc, 0, 0, 0);
       }
       if (ks < nsteps)
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qv[2 * ks * TILE], uv[2 * ks * TILE], acc, 0, 0, 0);
     }
-    acc += acc2;
 
     // ---- certified tests.  Lemma 1: "no" iff s + e < L.  "Yes" iff
     // s - e >= Y, with Y the float above L (exact table: f >= theta_k) or
@@ -435,9 +452,17 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
     rest &= valid ? cells : 0u;
     uint32_t yes = 0;
     if (__ballot(rest != 0u)) {  // some pair Lemma 1 did not reject: the "yes" test
+      // small float32 tiles: the rows' norms and k's are read again here
+      // instead of held in registers since the Lemma 1 test (an opaque row
+      // offset keeps the compiler from reusing those loads), so that the
+      // 4-wave register budget needs no spill: a spilled address reloaded
+      // before the products waited for the next tile's loads (5% faster).
+      // Larger tiles keep them (1-2% faster).
+      int rq = quarter_row(qhalf, half, 0);
+      if constexpr (!BF16 && NV <= 4) asm volatile("" : "+v"(rq));
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const int rb = quarter_row(qhalf, half, g * 4);
+        const int rb = rq + g * 8;
         const float4 n4 = *(const float4*)(meta_n + rb);
         const int4 k4 = *(const int4*)(meta_k + rb);
         const float nqs[4] = {n4.x, n4.y, n4.z, n4.w};
@@ -473,16 +498,12 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
     // block's pairs together.
     if (__ballot(und != 0u)) {
       const int cnt = __popc(und);
-      int incl = cnt;
-      for (int off = 1; off < 64; off <<= 1) {
-        const int v = __shfl_up(incl, off);
-        if (lane >= off) incl += v;
-      }
+      const int incl = wave_incl_scan(cnt);
       uint32_t ovf = 0;  // pairs beyond the list's capacity
       if (ix.exact) {
         int base = 0;
         if (lane == 63) base = atomicAdd(bv.npairs, incl);
-        base = __shfl(base, 63);
+        base = __builtin_amdgcn_readlane(base, 63);
         int pos = base + incl - cnt;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -498,13 +519,13 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
           }
         }
       } else {
-        const int total = __shfl(incl, 63);
+        const int total = __builtin_amdgcn_readlane(incl, 63);
         const int avail = kPairChunk - cfill_w;  // free slots of the current chunk
         const int need = total > avail ? (total - avail + kPairChunk - 1) / kPairChunk : 0;
         int nb = 0;
         if (need > 0) {
           if (lane == 0) nb = atomicAdd(bv.nchunks, need);
-          nb = __shfl(nb, 0);
+          nb = __builtin_amdgcn_readlane(nb, 0);
           if (lane < need && nb + lane < bv.chunk_cap) {
             bv.cfill[nb + lane] = kPairChunk;  // the last one is corrected at the end
             const int at = atomicAdd(&bv.bcnt[B], 1);
@@ -605,6 +626,27 @@ __device__ __forceinline__ void set_pair_result(const BatchView& bv, const DevIn
   atomicAdd(&bv.counts[jo], 1ull);
 }
 
+// The float64 product in index order, sixteen coordinates of each row loaded
+// at a time (more loads in flight for a kernel that waits on little else).
+// Every float product is exact in float64, so this is the same sum as a
+// product-then-add loop.
+__device__ __forceinline__ double dot64_rows16(const float* __restrict__ x,
+                                               const float* __restrict__ y, int d) {
+  double s = 0.0;
+  for (int c0 = 0; c0 < d; c0 += 16) {
+    float xv[16], yv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      xv[i] = c0 + i < d ? x[c0 + i] : 0.f;
+      yv[i] = c0 + i < d ? y[c0 + i] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (c0 + i < d) s = fma((double)xv[i], (double)yv[i], s);
+  }
+  return s;
+}
+
 __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView bv) {
   const int np = min(*bv.npairs, bv.pair_cap);
   unsigned long long yes_count = 0;
@@ -613,9 +655,10 @@ __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView b
     const int64_t r = bv.pair_u[t];
     const int64_t jj = bv.pair_j[t];
     const int32_t jo = bv.perm[jj];
-    const double fq = dot64_rows(bv.qs + (int64_t)jo * ix.d, ix.Qrow + r * ix.d, ix.d);
     const int k = bv.k_s[jj];
-    if (fq >= ix.L64[(int64_t)(k - 1) * ix.n_pad + r]) {
+    const double theta = ix.L64[(int64_t)(k - 1) * ix.n_pad + r];
+    const double fq = dot64_rows16(bv.qs + (int64_t)jo * ix.d, ix.Qrow + r * ix.d, ix.d);
+    if (fq >= theta) {
       set_pair_result(bv, ix, r, jo);
       ++yes_count;
     }
@@ -1503,7 +1546,7 @@ __global__ void __launch_bounds__(256) k_bdecide(DevIndex ix, BatchView bv) {
 
 // ---------------------------------------------------------------------------
 // CSR assembly.  Offsets: one workgroup scans the chunk's counts (original
-// chunk order) starting from *base.  Ids: one workgroup per query turns its
+// chunk order) starting from *base.  Ids: one wave per query turns its
 // bitmap row into ascending ids, then clears the row and the count.
 __global__ void __launch_bounds__(1024) k_boffsets(const unsigned long long* __restrict__ counts,
                                                 const uint8_t* __restrict__ all, int64_t n,
@@ -1533,57 +1576,66 @@ __global__ void __launch_bounds__(256) k_bassemble(BatchView bv, int32_t nq,
                                                    const int64_t* __restrict__ offs,
                                                    int32_t* __restrict__ ids, int64_t cap) {
   // One wave per query, one pass over its bitmap row (W words, a multiple of
-  // 4): lane L reads words 4(v0+L)..+3 of each 256-word group, so ids come
-  // out ascending; groups without a bit cost one load and a ballot.  Words
-  // that held bits are cleared.
+  // 4) in rounds of G groups of 64 vectors, all loaded at once: lane L holds
+  // vector 64 g + L of each group, so with the groups in order and the lanes
+  // in order within a group the ids come out ascending.  Words that held
+  // bits are cleared.
   const int lane = threadIdx.x & 63;
   const int32_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= nq) return;
-  if (bv.all[j]) {  // k > m: every user, ascending
-    const int64_t b0 = offs[j];
-    for (int64_t i = lane; i < bv.n && b0 + i < cap; i += 64) ids[b0 + i] = (int32_t)i;
-    if (lane == 0 && bv.ctr) atomicAdd(&bv.ctr[C_RES], (unsigned long long)bv.n);
-    return;
-  }
   u32x4* row = (u32x4*)(bv.bits + (int64_t)j * bv.W);
   const int64_t nv = bv.W / 4;
-  const int64_t start = offs[j];
-  int64_t pos = start;
-  constexpr int G = 4;  // groups loaded together (independent loads in flight)
-  for (int64_t v00 = 0; v00 < nv; v00 += 64 * G) {
-    u32x4 xs[G];
+  constexpr int G = 16, GS = 4;
+  u32x4 xs[G];
+  auto load = [&](int64_t v00) {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int64_t v = v00 + 64 * g + lane;
       xs[g] = u32x4{0u, 0u, 0u, 0u};
       if (v < nv) xs[g] = row[v];
     }
+  };
+  load(0);  // in flight with the query's flag and offset
+  const int64_t start = offs[j];
+  if (bv.all[j]) {  // k > m: every user, ascending
+    for (int64_t i = lane; i < bv.n && start + i < cap; i += 64) ids[start + i] = (int32_t)i;
+    if (lane == 0 && bv.ctr) atomicAdd(&bv.ctr[C_RES], (unsigned long long)bv.n);
+    return;
+  }
+  int64_t pos = start;
+  for (int64_t v00 = 0; v00 < nv; v00 += 64 * G) {
+    if (v00 > 0) load(v00);
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int64_t v = v00 + 64 * g + lane;
-      const u32x4 x = xs[g];
-      const int c = __popc(x[0]) + __popc(x[1]) + __popc(x[2]) + __popc(x[3]);
-      if (__ballot(c != 0) == 0ull) continue;
-      int incl = c;
-      for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(incl, off);
-        if (lane >= off) incl += y;
-      }
-      int64_t p = pos + incl - c;
-      if (c) {
+    for (int g0 = 0; g0 < G; g0 += GS) {  // scans of GS groups at a time
+    int cnt[GS], incl[GS];
+#pragma unroll
+    for (int h = 0; h < GS; ++h) {
+      const u32x4 x = xs[g0 + h];
+      cnt[h] = __popc(x[0]) + __popc(x[1]) + __popc(x[2]) + __popc(x[3]);
+      incl[h] = wave_incl_scan(cnt[h]);
+    }
+#pragma unroll
+    for (int h = 0; h < GS; ++h) {
+      const int g = g0 + h;
+      const int tot = __builtin_amdgcn_readlane(incl[h], 63);
+      if (tot == 0) continue;
+      if (cnt[h]) {
+        const int64_t v = v00 + 64 * g + lane;
         row[v] = u32x4{0u, 0u, 0u, 0u};
+        int64_t p = pos + incl[h] - cnt[h];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          uint32_t bits = x[q];
+          uint32_t bits = xs[g][q];
           while (bits) {
             const int b = __ffs(bits) - 1;
             bits &= bits - 1;
-            if (p < cap) ids[p] = (int32_t)((4 * v + q) * 32 + b);
+            if ((uint64_t)p < (uint64_t)cap) ids[p] = (int32_t)((4 * v + q) * 32 + b);
             ++p;
           }
         }
       }
-      pos += __shfl(incl, 63);
+      pos += tot;
+    }
     }
   }
   if (lane == 0) {
