@@ -626,27 +626,6 @@ __device__ __forceinline__ void set_pair_result(const BatchView& bv, const DevIn
   atomicAdd(&bv.counts[jo], 1ull);
 }
 
-// The float64 product in index order, sixteen coordinates of each row loaded
-// at a time (more loads in flight for a kernel that waits on little else).
-// Every float product is exact in float64, so this is the same sum as a
-// product-then-add loop.
-__device__ __forceinline__ double dot64_rows16(const float* __restrict__ x,
-                                               const float* __restrict__ y, int d) {
-  double s = 0.0;
-  for (int c0 = 0; c0 < d; c0 += 16) {
-    float xv[16], yv[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      xv[i] = c0 + i < d ? x[c0 + i] : 0.f;
-      yv[i] = c0 + i < d ? y[c0 + i] : 0.f;
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i)
-      if (c0 + i < d) s = fma((double)xv[i], (double)yv[i], s);
-  }
-  return s;
-}
-
 __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView bv) {
   const int np = min(*bv.npairs, bv.pair_cap);
   unsigned long long yes_count = 0;
@@ -655,10 +634,9 @@ __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView b
     const int64_t r = bv.pair_u[t];
     const int64_t jj = bv.pair_j[t];
     const int32_t jo = bv.perm[jj];
+    const double fq = dot64_rows(bv.qs + (int64_t)jo * ix.d, ix.Qrow + r * ix.d, ix.d);
     const int k = bv.k_s[jj];
-    const double theta = ix.L64[(int64_t)(k - 1) * ix.n_pad + r];
-    const double fq = dot64_rows16(bv.qs + (int64_t)jo * ix.d, ix.Qrow + r * ix.d, ix.d);
-    if (fq >= theta) {
+    if (fq >= ix.L64[(int64_t)(k - 1) * ix.n_pad + r]) {
       set_pair_result(bv, ix, r, jo);
       ++yes_count;
     }
