@@ -49,6 +49,20 @@ def test_batch_ragged_shapes_and_k_above_m(n, m, d, kmax, lb, prec):
     idx.free()
 
 
+@pytest.mark.parametrize("lb,prec", [(0, "fp32"), (0, "bf16"), (20, "fp32")])
+def test_batch_dense_results_over_several_assembly_rounds(lb, prec):
+    # k close to m: most users are members, so bitmap words and lanes hold
+    # many bits; 140,000 users take two rounds of the CSR assembly's loads
+    # (16 groups of 64 lanes x 128 users each)
+    w = datagen.workload(140_000, 40, 8, 0.5, 6, seed=11)
+    ks = np.array([30, 25, 40, 20, 35, 39], np.int32)
+    idx = Index.build(w.Q, w.P, 40, lb_items=lb, precision=prec)
+    off, ids = idx.reverse_kmips_batch(w.queries, ks)
+    assert off[-1] > 300_000  # dense rows
+    check_csr(w.Q, w.P, w.queries, ks, off, ids)
+    idx.free()
+
+
 def test_batch_several_chunks():
     # more queries than one chunk (4096), small catalog
     w = datagen.workload(300, 150, 12, 0.6, 150, seed=12)
