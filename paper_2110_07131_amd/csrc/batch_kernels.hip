@@ -571,6 +571,11 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
           atomicOr(&bv.bits[(int64_t)jo * bv.W + (orig_u >> 5)], 1u << (orig_u & 31));
           atomicAdd(&bv.counts[jo], 1ull);
         }
+        // this path's loads are all complete here: without the explicit
+        // wait the compiler's analysis keeps them pending around the tile
+        // loop and waits for every load before the next tile's products,
+        // the prefetched tile's included
+        __builtin_amdgcn_s_waitcnt(0);
       }
     }
 
