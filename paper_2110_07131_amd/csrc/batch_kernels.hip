@@ -252,6 +252,8 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
   return x;
 }
 
+constexpr int kExactRun = 64;  // exact table: pair slots a filter wave reserves at a time
+
 __device__ __forceinline__ int quarter_row(int qhalf, int half, int r) {
   return qhalf * 32 + (r / 4) * 8 + half * 4 + (r % 4);
 }
@@ -358,6 +360,9 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
 
   // bounded table: this wave's current pair chunk and its fill
   int ccur = -1, cfill_w = kPairChunk;
+  // exact table: this wave's current run of reserved pair slots
+  // [erun0, erun0 + erun), of which efill are used
+  int erun0 = 0, erun = 0, efill = 0;
 
   int T = next_live(masks, 0, nT), slot = 0;
   int Tn = next_live(masks, T + 1, nT);
@@ -501,13 +506,25 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
       const int incl = wave_incl_scan(cnt);
       uint32_t ovf = 0;  // pairs beyond the list's capacity
       if (ix.exact) {
-        int base = 0;
-        if (lane == 63) base = atomicAdd(bv.npairs, incl);
-        base = __builtin_amdgcn_readlane(base, 63);
-        int pos = base + incl - cnt;
+        // slots come from the wave's run of reserved slots, and a new run
+        // only when it is used up: the returning atomic's wait covers every
+        // load in flight, the next tile's prefetch included (vector memory
+        // returns in order), so one per tile with such pairs cost the bf16
+        // filter 11-21%
+        const int total = __builtin_amdgcn_readlane(incl, 63);
+        const int avail = erun - efill;
+        int nb = 0, need = 0;
+        if (total > avail) {
+          need = (total - avail + kExactRun - 1) / kExactRun * kExactRun;
+          if (lane == 0) nb = atomicAdd(bv.npairs, need);
+          nb = __builtin_amdgcn_readlane(nb, 0);
+        }
+        int p = incl - cnt;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           if ((und >> r) & 1u) {
+            const int pos = p < avail ? erun0 + efill + p : nb + (p - avail);
+            ++p;
             if (pos < bv.pair_cap) {
               bv.pair_u[pos] = (int32_t)u;
               bv.pair_j[pos] = (int32_t)((int64_t)T * TILE + quarter_row(qhalf, half, r));
@@ -515,8 +532,14 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
             } else {
               ovf |= 1u << r;
             }
-            ++pos;
           }
+        }
+        if (need > 0) {
+          erun0 = nb;
+          erun = need;
+          efill = total - avail;
+        } else {
+          efill += total;
         }
       } else {
         const int total = __builtin_amdgcn_readlane(incl, 63);
@@ -599,6 +622,10 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
     }
   }
   if (!ix.exact && lane == 0 && ccur >= 0 && ccur < bv.chunk_cap) bv.cfill[ccur] = cfill_w;
+  // exact table: the unused end of the wave's last run holds no pair
+  if (ix.exact)
+    for (int i = efill + lane; i < erun; i += 64)
+      if (erun0 + i < bv.pair_cap) bv.pair_u[erun0 + i] = -1;
 
   if (bv.ctr) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -637,6 +664,7 @@ __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView b
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < np;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = bv.pair_u[t];
+    if (r < 0) continue;  // an unused reserved slot
     const int64_t jj = bv.pair_j[t];
     const int32_t jo = bv.perm[jj];
     const double fq = dot64_rows(bv.qs + (int64_t)jo * ix.d, ix.Qrow + r * ix.d, ix.d);
@@ -1769,7 +1797,10 @@ static void bscan_nv(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
 void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
   if (ix.nB == 0) return;
   if (ix.exact) {
-    hipLaunchKernelGGL(k_brecheck_exact, dim3(256), dim3(256), 0, s, ix, bv);
+    // a thread per slot of the whole list (most of its blocks exit at once):
+    // the filter waves' reserved runs leave unused slots between the pairs
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((bv.pair_cap + 255) / 256, 1 << 20));
+    hipLaunchKernelGGL(k_brecheck_exact, dim3((unsigned)blocks), dim3(256), 0, s, ix, bv);
     return;
   }
   const int per_thread = (ix.d * (TILE / 4) + 255) / 256;  // 16-byte vectors of an item tile
