@@ -79,11 +79,14 @@ def test_batch_several_chunks():
 
 
 @pytest.mark.parametrize("lb,prec", MODES)
-def test_pair_list_overflow_falls_back_to_float64(lb, prec):
+@pytest.mark.parametrize("cap", [3, 100])
+def test_pair_list_overflow_falls_back_to_float64(lb, prec, cap):
+    # cap 3: the first reserved run of pair slots already crosses the end of
+    # the list; cap 100: some runs fit, a later one crosses it
     w = datagen.workload(500, 200, 16, 0.5, 16, seed=4)
     rng = np.random.default_rng(4)
     ks = rng.integers(1, 9, len(w.qidx)).astype(np.int32)
-    idx = Index.build(w.Q, w.P, 8, lb_items=lb, precision=prec, pair_cap=3)
+    idx = Index.build(w.Q, w.P, 8, lb_items=lb, precision=prec, pair_cap=cap)
     off, ids = idx.reverse_kmips_batch(w.queries, ks)
     check_csr(w.Q, w.P, w.queries, ks, off, ids)
     idx.free()
