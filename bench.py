@@ -1,15 +1,18 @@
 """Benchmark: exact reverse k-MIPS queries/sec on one MI355X.
 
-Workload (default): 100,000 users x 20,000 items, d = 50, log-normal norms
-(sigma 0.5), k_max = 25; 1,000 query items drawn from P, each evaluated at
-k = 1, 5, 10 and 25 (4,000 queries).  The index is built once (offline,
-reported as build_ms, not part of the timed region).  A step is one pass of
-the whole online path over all 4,000 queries, with queries, k values and
-outputs resident on the device, results in CSR form in device memory.
+Workload (default, the largest single-index workload): 1,000,000 users x
+100,000 items, d = 100, log-normal norms (sigma 0.5), k_max = 25; 1,000 query
+items drawn from P, each evaluated at k = 1, 10 and 25 (3,000 queries), float32
+bulk products, exact result sets.  The index is built once (offline, reported
+as build_ms, not part of the timed region).  A step is one pass of the whole
+online path over all 3,000 queries, with queries, k values and outputs
+resident on the device, results in CSR form in device memory.
 
-Prints one JSON line.  Also reports: per-query latency (p50/p99) of the
-one-query host API, the dominant kernel's roofline fraction from per-kernel
-HIP events in the same run, and the CPU oracle timed on the host cores.
+Prints one JSON line.  Also reports: the batch latency (p50/p99 of single
+steps), the one-query host API latency, the same workload with bf16 bulk
+products and with the paper's short lower-bound prefix, the dominant
+kernel's roofline fraction from per-kernel HIP events in the same run, and
+the CPU oracle (the exact top-k_max table form) timed on the host cores.
 """
 from __future__ import annotations
 
@@ -33,12 +36,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="plain")
+    ap.add_argument("--config", default="precision")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--lb-items", type=int, default=0,
                     help="|P'| of the lower-bound arrays; 0 = all items (exact table)")
     ap.add_argument("--latency-queries", type=int, default=1000)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU seconds of each oracle table build (all cores, then one core)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the bf16 and short-prefix runs of the same workload")
+    ap.add_argument("--form-steps", type=int, default=5)
     ap.add_argument("--handoff-tiles", type=int, default=0,
                     help="index option handoff_tiles (bounded table; 0 = the library default)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -111,20 +118,84 @@ def measured_traffic(kernel: str, key: str):
     return e["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(w, ks, budget_s: float) -> dict:
+def cpu_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "os_cpu_count": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def theta_oracle_timing(w, ks, kmax: int, threads: int, budget_s: float, seed: int) -> dict:
+    """The table form of the oracle (exact top-k_max values of every user over
+    all of P in float64, then one order-statistic test per user and query)
+    with `threads` OpenMP threads.  Both phases are linear in the number of
+    users, so each is timed on a part of them and scaled by n / part:
+      * table build: a uniform user sample sized from a probe so that the
+        build takes about budget_s;
+      * query phase: the first (q, k) queries over a larger block of users
+        (the sampled table rows repeated: its cost does not depend on the
+        values), so that the per-call overhead stays small against the work."""
     import oracle
-    threads = oracle.num_threads()
-    done, t0 = 0, time.perf_counter()
+    oracle.set_threads(threads)
+    used = oracle.num_threads()
+    n = w.Q.shape[0]
+    rng = np.random.default_rng(seed)
     qs = w.queries
-    while done < len(ks):
-        oracle.brute(w.Q, w.P, qs[done], int(ks[done]))
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"brute-force definition (float64) on the first {done} of the "
-                      f"{len(ks)} (q,k) queries of the same workload, {dt:.1f} s"}
+    probe = int(min(n, max(64 * used, 64)))
+    Qp = np.ascontiguousarray(w.Q[rng.choice(n, probe, replace=False)])
+    oracle.theta(Qp[:used], w.P, kmax)  # thread start-up outside the probe
+    t0 = time.perf_counter()
+    oracle.theta(Qp, w.P, kmax)
+    per_user = (time.perf_counter() - t0) / probe
+    S = int(min(n, max(probe, budget_s / max(per_user, 1e-9))))
+    Qs = np.ascontiguousarray(w.Q[np.sort(rng.choice(n, S, replace=False))])
+    t0 = time.perf_counter()
+    th = oracle.theta(Qs, w.P, kmax)
+    tb = time.perf_counter() - t0
+    Sq = int(min(n, 100_000 if used > 1 else 20_000))
+    nq_t = int(min(len(ks), 300))
+    Qq = np.ascontiguousarray(w.Q[:Sq])
+    thq = np.ascontiguousarray(th[np.arange(Sq) % S])
+    t0 = time.perf_counter()
+    for i in range(nq_t):
+        oracle.theta_query(thq, Qq, qs[i], int(ks[i]))
+    tq = time.perf_counter() - t0
+    return {"threads": used, "sample_users": S, "table_build_s_sample": tb,
+            "query_users": Sq, "query_count": nq_t, "query_phase_s_sample": tq,
+            "build_s_full": tb * n / S, "query_ms_full": 1e3 * tq / nq_t * n / Sq,
+            "queries_per_s_full": nq_t / (tq * n / Sq)}
+
+
+def cpu_baseline(w, ks, kmax: int, budget_s: float) -> dict:
+    import oracle
+    info = cpu_info()
+    allc = theta_oracle_timing(w, ks, kmax, oracle.num_threads(), budget_s, seed=7)
+    one = theta_oracle_timing(w, ks, kmax, 1, budget_s, seed=8)
+    oracle.set_threads(allc["threads"])
+    return {"value": allc["queries_per_s_full"], "unit": "queries/s", "cores": allc["threads"],
+            "kind": "oracle",
+            "sample": (f"table form of the float64 oracle, {allc['threads']} threads: table build "
+                       f"over {allc['sample_users']} sampled users ({allc['table_build_s_sample']:.1f} s), "
+                       f"query phase of the first {allc['query_count']} (q,k) over "
+                       f"{allc['query_users']} users ({allc['query_phase_s_sample']:.2f} s); one core: "
+                       f"{one['sample_users']} and {one['query_users']} users; each scaled by n / users "
+                       f"to the full workload.  value = query phase only (the table is built offline, "
+                       f"like the index); build_s_full = the table build"),
+            "build_s_full": allc["build_s_full"], "query_ms_full": allc["query_ms_full"],
+            "one_core": {"value": one["queries_per_s_full"], "build_s_full": one["build_s_full"],
+                         "query_ms_full": one["query_ms_full"], "sample_users": one["sample_users"]},
+            **info}
 
 
 def serve_main(args):
@@ -345,6 +416,21 @@ def main():
     roofline["traffic"] = measured_traffic(roofline["kernel"], f"{args.config}/{args.precision}/{table}")
     kernel_share = {c: {"ms_per_step": v[0], "launches": v[1]} for c, v in kt.items()}
 
+    # Batch latency: every query of a step completes when its step does; the
+    # steps again, one at a time, each bracketed by device synchronisations.
+    bt = []
+    for _ in range(max(args.steps, 1)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        bt.append(time.perf_counter() - t)
+    bt = np.array(bt) * 1e3
+    batch_lat = {"p50_ms": float(np.percentile(bt, 50)), "p99_ms": float(np.percentile(bt, 99)),
+                 "steps": len(bt),
+                 "what": f"one device-resident step of {nq} queries (launch to completion); "
+                         f"every query of the step completes with it"}
+
     lat = None
     if not args.no_latency:
         nl = min(args.latency_queries, nq)
@@ -357,8 +443,43 @@ def main():
         lat = {"p50_ms": float(np.percentile(times, 50)), "p99_ms": float(np.percentile(times, 99)),
                "qps": nl / (times.sum() / 1e3), "queries": nl,
                "what": "one query at a time through the host API (H2D of q, ids on host)"}
+    idx.free()
+    del ids, offsets
 
-    cpu = None if args.no_cpu else cpu_baseline(w, ks, args.cpu_seconds)
+    # The same workload in the other forms: bf16 bulk products with float64
+    # rechecks, and the paper's index (P' = 2 k_max items in the lower-bound
+    # arrays, linear scans), each timed over a few steps and checked on a
+    # sample against the host API.
+    forms = {}
+    if not args.no_forms:
+        for name, prec, lb in (("bf16_exact_table", "bf16", 0),
+                               ("fp32_paper_index", "fp32", 2 * kmax)):
+            if prec == args.precision and lb == args.lb_items:
+                continue
+            fi = Index.build(w.Q, w.P, kmax, precision=prec, lb_items=lb)
+            foff = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+            fids = torch.empty(cap, dtype=torch.int32, device=dev)
+            fi.reverse_kmips_batch_dev(qs, ks, foff, fids, stream)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.form_steps):
+                fi.reverse_kmips_batch_dev(qs, ks, foff, fids, stream)
+            torch.cuda.synchronize()
+            fel = time.perf_counter() - t
+            fo = foff.cpu().numpy()
+            fh = fids[:int(fo[-1])].cpu().numpy()
+            for i in np.linspace(0, nq - 1, 4).astype(int):
+                ref = fi.reverse_kmips(qs_np[i], int(ks[i]))
+                assert np.array_equal(fh[fo[i]:fo[i + 1]], ref), f"{name}: batch/single mismatch at {i}"
+            forms[name] = {"value": nq * args.form_steps / fel, "unit": "queries/s",
+                           "ms_per_step": 1e3 * fel / args.form_steps, "steps": args.form_steps,
+                           "precision": prec, "lb_items": lb or m}
+            print(f"[bench] form {name}: {forms[name]['ms_per_step']:.3f} ms/step, "
+                  f"{forms[name]['value']:.0f} queries/s", file=sys.stderr, flush=True)
+            fi.free()
+            del foff, fids
+
+    cpu = None if args.no_cpu else cpu_baseline(w, ks, kmax, args.cpu_seconds)
 
     line = {
         "metric": "reverse k-MIPS queries/sec (exact sets) and p50/p99 latency at 1 MI355X",
@@ -367,12 +488,16 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": args.precision.replace("fp", "f"),
         "data": "synthetic",
         "config": {"workload": f"{args.config}: |Q|={n} |P|={m} d={d} k_max={kmax} "
-                               f"lognormal-norm Gaussian vectors, seed 0, {nq // len(set(ks.tolist())) if args.config == 'plain' else nq} "
-                               f"query items from P x k in {sorted(set(ks.tolist())) if len(set(ks.tolist())) < 8 else '1..' + str(kmax)}",
+                               f"lognormal-norm (sigma {cfg['sigma']}) Gaussian vectors, seed 0, "
+                               f"{len(np.unique(w.qidx))} query items from P x k in "
+                               f"{sorted(set(ks.tolist())) if len(set(ks.tolist())) < 8 else '1..' + str(kmax)}; "
+                               f"{args.precision} bulk products, "
+                               f"{'exact' if args.lb_items in (0, m) else 'P=' + str(args.lb_items)} lower-bound table",
                    "queries_per_step": nq, "lb_items": args.lb_items or m,
                    "precision": args.precision, "form": "device-resident batch, CSR output"},
-        "p50_ms": lat["p50_ms"] if lat else None, "p99_ms": lat["p99_ms"] if lat else None,
-        "latency": lat,
+        "p50_ms": batch_lat["p50_ms"], "p99_ms": batch_lat["p99_ms"],
+        "latency": batch_lat, "single_query_latency": lat,
+        "other_forms": forms,
         "roofline": roofline,
         "dominant_kernel_class": dom,
         "kernel_time_per_step": kernel_share,

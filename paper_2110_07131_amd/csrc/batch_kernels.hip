@@ -28,7 +28,7 @@ __device__ __forceinline__ unsigned long long lanemask_lt_b() {
 // ---------------------------------------------------------------------------
 // Per query of the chunk: |q| rounded up (one wave per query).
 __global__ void k_bnorms(const float* __restrict__ qs, int32_t nq, int32_t d,
-                         float* __restrict__ qn, int32_t* __restrict__ npairs) {
+                         float* __restrict__ qn, unsigned long long* __restrict__ npairs) {
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (j == 0 && lane == 0) *npairs = 0;
@@ -252,7 +252,6 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
   return x;
 }
 
-constexpr int kExactRun = 64;  // exact table: pair slots a filter wave reserves at a time
 
 __device__ __forceinline__ int quarter_row(int qhalf, int half, int r) {
   return qhalf * 32 + (r / 4) * 8 + half * 4 + (r % 4);
@@ -362,7 +361,8 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   int ccur = -1, cfill_w = kPairChunk;
   // exact table: this wave's current run of reserved pair slots
   // [erun0, erun0 + erun), of which efill are used
-  int erun0 = 0, erun = 0, efill = 0;
+  int64_t erun0 = 0;
+  int erun = 0, efill = 0;
 
   int T = next_live(masks, 0, nT), slot = 0;
   int Tn = next_live(masks, T + 1, nT);
@@ -513,17 +513,21 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
         // filter 11-21%
         const int total = __builtin_amdgcn_readlane(incl, 63);
         const int avail = erun - efill;
-        int nb = 0, need = 0;
+        int need = 0;
+        int64_t nb = 0;
         if (total > avail) {
           need = (total - avail + kExactRun - 1) / kExactRun * kExactRun;
-          if (lane == 0) nb = atomicAdd(bv.npairs, need);
-          nb = __builtin_amdgcn_readlane(nb, 0);
+          unsigned long long got = 0;
+          if (lane == 0) got = atomicAdd(bv.npairs, (unsigned long long)need);
+          const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)got, 0);
+          const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(got >> 32), 0);
+          nb = (int64_t)(((uint64_t)hi << 32) | lo);
         }
         int p = incl - cnt;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           if ((und >> r) & 1u) {
-            const int pos = p < avail ? erun0 + efill + p : nb + (p - avail);
+            const int64_t pos = p < avail ? erun0 + efill + p : nb + (p - avail);
             ++p;
             if (pos < bv.pair_cap) {
               bv.pair_u[pos] = (int32_t)u;
@@ -659,7 +663,7 @@ __device__ __forceinline__ void set_pair_result(const BatchView& bv, const DevIn
 }
 
 __global__ void __launch_bounds__(256) k_brecheck_exact(DevIndex ix, BatchView bv) {
-  const int np = min(*bv.npairs, bv.pair_cap);
+  const int64_t np = (int64_t)min(*bv.npairs, (unsigned long long)bv.pair_cap);
   unsigned long long yes_count = 0;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < np;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -1797,9 +1801,9 @@ static void bscan_nv(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
 void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
   if (ix.nB == 0) return;
   if (ix.exact) {
-    // a thread per slot of the whole list (most of its blocks exit at once):
-    // the filter waves' reserved runs leave unused slots between the pairs
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((bv.pair_cap + 255) / 256, 1 << 20));
+    // grid-stride over the used part of the list (the reserved runs leave
+    // unused slots, marked -1, between the pairs)
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((bv.pair_cap + 255) / 256, 2048));
     hipLaunchKernelGGL(k_brecheck_exact, dim3((unsigned)blocks), dim3(256), 0, s, ix, bv);
     return;
   }

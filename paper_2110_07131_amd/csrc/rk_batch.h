@@ -7,6 +7,7 @@ namespace rk {
 constexpr int kBatchChunkMax = 4096;  // queries per chunk (single-workgroup sort in LDS)
 constexpr int kPairChunk = 256;       // slots per pair chunk (bounded table)
 constexpr int kUserPairs = 8;         // flagged-pair slots per user in the scan's long pass
+constexpr int kExactRun = 64;         // exact table: pair slots a filter wave reserves at a time
 
 // Scan list length per user: k_max + 2 rounded up to a multiple of 4.
 __host__ __device__ inline int bscan_list_len(int kmax) { return (kmax + 2 + 3) / 4 * 4; }
@@ -26,7 +27,8 @@ struct BatchView {
   unsigned long long* counts;   // [nq] result sizes, caller order
   uint8_t* all;                 // [nq] 1 if k > m (every user is a member)
   int64_t n;                    // users
-  int32_t* npairs;              // undecided pairs appended (may exceed cap)
+  unsigned long long* npairs;   // exact table: pair slots reserved (may exceed cap;
+                                // 64-bit: a chunk can reserve more than 2^31)
   int32_t pair_cap;
   int32_t* pair_u;              // sorted user index
   int32_t* pair_j;              // sorted query position

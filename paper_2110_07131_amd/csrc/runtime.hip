@@ -100,7 +100,8 @@ struct rk_index {
     int64_t pair_cap = 0;
     float *qn = nullptr, *qt = nullptr, *qn_s = nullptr, *pair_s = nullptr;
     uint16_t* qb = nullptr;
-    int32_t *perm = nullptr, *k_s = nullptr, *kofs_s = nullptr, *npairs = nullptr, *pair_u = nullptr,
+    unsigned long long* npairs = nullptr;
+    int32_t *perm = nullptr, *k_s = nullptr, *kofs_s = nullptr, *pair_u = nullptr,
             *pair_j = nullptr, *ks_dev = nullptr;
     // bounded table: chunked pair slots, per-block chunk lists
     int32_t *pair_st = nullptr, *cfill = nullptr, *nchunks = nullptr, *bcnt = nullptr,
@@ -513,6 +514,10 @@ BatchSizes batch_sizes(const rk_index* h, int32_t chunk) {
   const int64_t cp = round_up(chunk, TILE), W = bitmap_words(ix.n);
   int64_t pc = std::min<int64_t>((int64_t)chunk * std::max<int64_t>(ix.n_pad, 1),
                                  ix.exact ? kPairBudgetExact : kPairBudget);
+  // exact table: each of a block's four filter waves may leave up to
+  // kExactRun - 1 slots of its last reserved run unused
+  // (bounded so that very large catalogs keep a modest list)
+  if (ix.exact) pc += std::min<int64_t>(4 * (int64_t)ix.nB * kExactRun, 3 * kPairBudgetExact);
   if (h->opts.pair_cap > 0) pc = h->opts.pair_cap;
   if (!ix.exact) {
     // Chunks of kPairChunk slots: every chunk is full but the one each of a
@@ -527,7 +532,7 @@ BatchSizes batch_sizes(const rk_index* h, int32_t chunk) {
   z.pc = pc;
   const int64_t d2 = ix.d + (ix.d & 1);
   int64_t b = chunk * 4 * 2 + cp * d2 * 4 + (ix.bf16 ? cp * ix.d16 * 2 : 0) + cp * 12 +
-              chunk * W * 4 + chunk * 8 + chunk + 4 + pc * 12 + chunk * 4;
+              chunk * W * 4 + chunk * 8 + chunk + 8 + pc * 12 + chunk * 4;
   if (!ix.exact)
     b += std::max<int64_t>(pc, 1) * 4 + std::max<int64_t>(z.chunk_cap, 1) * 4 + 4 +
          std::max<int64_t>(ix.nB, 1) * 4 * (1 + z.maxc) +

@@ -92,6 +92,40 @@ def test_pair_list_overflow_falls_back_to_float64(lb, prec, cap):
     idx.free()
 
 
+def test_exact_pair_counter_beyond_int32():
+    # margin_rel = 0.49 on nearly parallel and antiparallel vectors leaves
+    # every (user, query) pair undecided (every block holds users of both
+    # directions, so Lemma 3 prunes nothing): 4,096 queries x 540,000 users
+    # reserve more than 2^31 pair slots in one query chunk.  The first ones
+    # fit the list (float64 recheck), the filter decides the rest in float64
+    # itself; the reserve counter must not wrap.
+    rng = np.random.default_rng(90)
+    n, m, d, nq = 540_000, 64, 4, 4096
+    sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)[:, None]
+    Q = (sign * (1 + 0.01 * rng.standard_normal((n, d)))).astype(np.float32)
+    P = (1 + 0.01 * rng.standard_normal((m, d))).astype(np.float32)
+    qs = np.ascontiguousarray(P[rng.integers(0, m, nq)])
+    ks = rng.integers(1, 3, nq).astype(np.int32)
+    idx = Index.build(Q, P, 4, margin_rel=0.49)
+    idx.set_counting(True)
+    off, ids = idx.reverse_kmips_batch(qs, ks)
+    st = idx.stats()
+    assert st["blocks_pruned"] == 0 and st["lemma1_no"] == 0
+    assert st["rechecks"] == nq * n > 2 ** 31
+    # oracle on 3,000 users: the first and last norm-sorted blocks and a sample
+    perm = oracle.sort_desc(oracle.sqnorms(Q))
+    edge = np.concatenate([perm[:64], perm[(n - 1) // 64 * 64:]])
+    us = np.union1d(edge, rng.choice(n, 3000 - edge.size, replace=False)).astype(np.int32)
+    th = oracle.theta(np.ascontiguousarray(Q[us]), P, 4)
+    assert off[0] == 0 and np.all(np.diff(off) >= 0)
+    for i in range(nq):
+        row = ids[off[i]:off[i + 1]]
+        assert np.all(np.diff(row) > 0), i
+        want = us[oracle.theta_query(th, np.ascontiguousarray(Q[us]), qs[i], int(ks[i]))]
+        assert np.array_equal(row[np.isin(row, us, assume_unique=True)], want), i
+    idx.free()
+
+
 @pytest.mark.parametrize("lb,prec", MODES)
 def test_batch_integer_ties(lb, prec):
     rng = np.random.default_rng(8)

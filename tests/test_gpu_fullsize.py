@@ -1,18 +1,31 @@
 """GPU parity at the full workload sizes, in the launch configuration that the
 benchmark times (device-resident queries, CSR output, the device batch entry
-point).  The oracle cannot evaluate every user of every query at these sizes,
-so each test draws a seeded sample of users, computes their exact top-k_max
-table over all of P in float64 (the definition through its order statistic),
-and requires every result set, restricted to the sample, to equal the
-oracle's; the CSR structure is checked in full."""
+point).
+
+* 100,000 users x 20,000 items: every user of every (q, k) is compared with
+  the oracle (the exact top-k_max table of all users over all of P in
+  float64, then the order-statistic test per query), in both table modes and
+  both bulk precisions, and three repeated runs must give bitwise-identical
+  CSR output.
+* 1,000,000 x 100,000 and 500,000 x 50,000: the oracle evaluates a seeded
+  sample of 10,000 users that always contains every user of the first and
+  the last norm-sorted block (the blocks with the largest and smallest
+  norms; the last one is partial when n is not a multiple of 64).  Each
+  result set, restricted to the sample, must equal the oracle's; the CSR
+  structure is checked in full.
+* The 500,000 x 50,000 (d = 100) serving catalog: requests through the
+  serving runtime, checked the same way on a 10,000-user sample.
+"""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2110_07131_amd import datagen
-from paper_2110_07131_amd.rkmips import Index
+from paper_2110_07131_amd.rkmips import Index, Server
 
 pytestmark = pytest.mark.gpu
+
+BLOCK = 64  # users per block
 
 
 def run_device_batch(idx, qs_np, ks, cap_per_query):
@@ -29,68 +42,156 @@ def run_device_batch(idx, qs_np, ks, cap_per_query):
     return off_h, ids[:int(off_h[-1])].cpu().numpy()
 
 
-def check_sampled(w, qs, ks, kmax, off, ids, n_sample, seed):
-    n = w.Q.shape[0]
-    assert off[0] == 0 and np.all(np.diff(off) >= 0)
-    rng = np.random.default_rng(seed)
-    us = np.sort(rng.choice(n, n_sample, replace=False)).astype(np.int32)
-    Qs = np.ascontiguousarray(w.Q[us])
-    th = oracle.theta(Qs, w.P, kmax)
-    for i in range(len(ks)):
+def check_csr_structure(off, ids, nq, n):
+    assert off.shape == (nq + 1,) and off[0] == 0 and np.all(np.diff(off) >= 0)
+    assert ids.shape == (off[-1],)
+    for i in range(nq):
         row = ids[off[i]:off[i + 1]]
-        assert np.all(np.diff(row) > 0), i                    # ascending, no duplicates
+        assert np.all(np.diff(row) > 0), i                     # ascending, no duplicates
         assert row.size == 0 or (row[0] >= 0 and row[-1] < n), i
-        want = us[oracle.theta_query(th, Qs, qs[i], int(ks[i]))]
-        got = row[np.isin(row, us, assume_unique=True)]
-        assert np.array_equal(got, want), (i, int(ks[i]), got[:8], want[:8])
 
 
-@pytest.mark.parametrize("lb,prec", [(0, "fp32"), (0, "bf16"), (50, "fp32"), (50, "bf16")])
-def test_plain_full_size(lb, prec):
-    # 100,000 users x 20,000 items, d = 50, 1,000 query items x k in {1,5,10,25}
+def user_sample(Q, n_sample, seed):
+    """Sorted original ids: the users of the first and last norm-sorted blocks
+    (descending squared norm, ties by id, as the index sorts them) plus a
+    seeded uniform sample of the others."""
+    n = Q.shape[0]
+    perm = oracle.sort_desc(oracle.sqnorms(Q))
+    last0 = (n - 1) // BLOCK * BLOCK
+    edge = np.unique(np.concatenate([perm[:BLOCK], perm[last0:]]))
+    rng = np.random.default_rng(seed)
+    others = np.setdiff1d(np.arange(n, dtype=np.int32), edge)
+    pick = rng.choice(others, n_sample - edge.size, replace=False)
+    return np.sort(np.concatenate([edge, pick])).astype(np.int32), perm
+
+
+class Sampled:
+    """Oracle membership of a user sample for a list of (q, k)."""
+
+    def __init__(self, w, kmax, n_sample, seed):
+        self.us, self.perm = user_sample(w.Q, n_sample, seed)
+        self.Qs = np.ascontiguousarray(w.Q[self.us])
+        self.th = oracle.theta(self.Qs, w.P, kmax)
+
+    def want(self, q, k):
+        return self.us[oracle.theta_query(self.th, self.Qs, q, int(k))]
+
+    def check(self, qs, ks, off, ids, n):
+        check_csr_structure(off, ids, len(ks), n)
+        for i in range(len(ks)):
+            row = ids[off[i]:off[i + 1]]
+            got = row[np.isin(row, self.us, assume_unique=True)]
+            want = self.want(qs[i], ks[i])
+            assert np.array_equal(got, want), (i, int(ks[i]), got[:8], want[:8])
+
+
+# --- 100,000 users x 20,000 items, d = 50: every user ------------------------
+
+@pytest.fixture(scope="module")
+def plain():
     c = datagen.CONFIGS["plain"]
     w = datagen.config_workload("plain")
     ks = w.ks.astype(np.int32)
+    th = oracle.theta(w.Q, w.P, c["k_max"])  # every user over every item
+    qs = w.queries
+    want = [oracle.theta_query(th, w.Q, qs[i], int(ks[i])) for i in range(len(ks))]
+    return c, w, ks, want
+
+
+@pytest.mark.parametrize("lb,prec", [(0, "fp32"), (0, "bf16"), (50, "fp32"), (50, "bf16")])
+def test_plain_full_size_every_user(plain, lb, prec):
+    # 1,000 query items x k in {1,5,10,25}: 4,000 result sets, all 100,000
+    # users each (1,563 blocks, the last one of 32 users)
+    c, w, ks, want = plain
     idx = Index.build(w.Q, w.P, c["k_max"], precision=prec, lb_items=lb)
     off, ids = run_device_batch(idx, w.queries, ks, 256)
-    check_sampled(w, w.queries, ks, c["k_max"], off, ids, 1000, seed=1)
+    check_csr_structure(off, ids, len(ks), w.Q.shape[0])
+    bad = [i for i in range(len(ks)) if not np.array_equal(ids[off[i]:off[i + 1]], want[i])]
+    assert not bad, (len(bad), bad[:5])
     idx.free()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_precision_config_full_size(prec):
-    # 1,000,000 users x 100,000 items, d = 100, 1,000 query items x k in {1,10,25}
+@pytest.mark.parametrize("lb,prec", [(0, "fp32"), (0, "bf16"), (50, "fp32")])
+def test_plain_full_size_bitwise_repeatable(plain, lb, prec):
+    # three runs of the benchmark's step give bitwise-identical CSR output
+    # (atomics order pairs and results differently from run to run; the
+    # assembled rows must not depend on it)
+    c, w, ks, want = plain
+    idx = Index.build(w.Q, w.P, c["k_max"], precision=prec, lb_items=lb)
+    runs = [run_device_batch(idx, w.queries, ks, 256) for _ in range(3)]
+    for off, ids in runs[1:]:
+        assert np.array_equal(off, runs[0][0]) and np.array_equal(ids, runs[0][1])
+    off, ids = runs[0]
+    assert all(np.array_equal(ids[off[i]:off[i + 1]], want[i]) for i in range(0, len(ks), 97))
+    idx.free()
+
+
+# --- 1,000,000 users x 100,000 items, d = 100: 10,000-user sample ------------
+
+@pytest.fixture(scope="module")
+def precision():
     c = datagen.CONFIGS["precision"]
     w = datagen.config_workload("precision")
-    ks = w.ks.astype(np.int32)
-    idx = Index.build(w.Q, w.P, c["k_max"], precision=prec)
+    return c, w, w.ks.astype(np.int32), Sampled(w, c["k_max"], 10_000, seed=2)
+
+
+@pytest.mark.parametrize("lb,prec", [(0, "fp32"), (0, "bf16"), (50, "fp32")])
+def test_precision_config_full_size(precision, lb, prec):
+    # 1,000 query items x k in {1,10,25}; lb = 50 is the paper's P' = 2 k_max:
+    # 3,000 queries in six query chunks, lists carried across them, and the
+    # last users of most blocks handed to group passes (1,563 item tiles)
+    c, w, ks, smp = precision
+    idx = Index.build(w.Q, w.P, c["k_max"], precision=prec, lb_items=lb)
+    if lb:
+        idx.set_counting(True)
     off, ids = run_device_batch(idx, w.queries, ks, 512)
-    check_sampled(w, w.queries, ks, c["k_max"], off, ids, 400, seed=2)
+    if lb:
+        assert idx.stats()["scan_handoff"] > 0
+    smp.check(w.queries, ks, off, ids, w.Q.shape[0])
     idx.free()
 
 
-def test_precision_config_full_size_short_prefix():
-    # the same workload with the paper's P' = 50: 3,000 queries in six query
-    # chunks, with lists carried across them, and the last users of most
-    # blocks handed to group passes (1,563 item tiles)
-    c = datagen.CONFIGS["precision"]
-    w = datagen.config_workload("precision")
-    ks = w.ks.astype(np.int32)
-    idx = Index.build(w.Q, w.P, c["k_max"], lb_items=50)
-    idx.set_counting(True)
-    off, ids = run_device_batch(idx, w.queries, ks, 512)
-    assert idx.stats()["scan_handoff"] > 0
-    check_sampled(w, w.queries, ks, c["k_max"], off, ids, 400, seed=4)
-    idx.free()
+# --- 500,000 users x 50,000 items, d = 200, sigma 0.8: 10,000-user sample ----
 
-
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_batched_config_full_size(prec):
-    # 500,000 users x 50,000 items, d = 200, sigma 0.8, 4,096 queries, k ~ U{1..50}
+@pytest.fixture(scope="module")
+def batched():
     c = datagen.CONFIGS["batched"]
     w = datagen.config_workload("batched")
-    ks = w.ks.astype(np.int32)
+    smp = Sampled(w, c["k_max"], 10_000, seed=3)
+    # 500,000 = 7,812 blocks + 32 users: the last block is partial
+    assert w.Q.shape[0] % BLOCK == 32
+    return c, w, w.ks.astype(np.int32), smp
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batched_config_full_size(batched, prec):
+    # 4,096 queries in one launch, k ~ U{1..50}
+    c, w, ks, smp = batched
     idx = Index.build(w.Q, w.P, c["k_max"], precision=prec)
     off, ids = run_device_batch(idx, w.queries, ks, 1024)
-    check_sampled(w, w.queries, ks, c["k_max"], off, ids, 400, seed=3)
+    smp.check(w.queries, ks, off, ids, w.Q.shape[0])
+    idx.free()
+
+
+# --- serving: the 500,000 x 50,000 (d = 100) catalog --------------------------
+
+def test_serving_mid_catalog_full_size():
+    c = datagen.CONFIGS["serve_mid"]
+    w = datagen.config_workload("serve_mid", n_queries=1500)
+    smp = Sampled(w, c["k_max"], 10_000, seed=5)
+    idx = Index.build(w.Q, w.P, c["k_max"])
+    srv = Server(max_batch=256)
+    cat = srv.add(idx)
+    qs, ks = w.queries, w.ks.astype(np.int32)
+    srv.submit_many([cat] * len(ks), list(qs), ks, np.arange(len(ks)))
+    got = {}
+    while len(got) < len(ks):
+        for tag, ci, status, ids, t0, t1 in srv.poll(wait_us=50000):
+            assert status == 0 and ci == cat and tag not in got
+            got[tag] = ids
+    srv.close()
+    off = np.zeros(len(ks) + 1, np.int64)
+    off[1:] = np.cumsum([got[i].size for i in range(len(ks))])
+    ids = np.concatenate([got[i] for i in range(len(ks))]) if len(ks) else np.zeros(0, np.int32)
+    smp.check(qs, ks, off, ids.astype(np.int32), w.Q.shape[0])
     idx.free()
