@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=10_000)
     ap.add_argument("--serve-warmup", type=int, default=1_000)
     ap.add_argument("--serve-batch", type=int, default=1024)
+    ap.add_argument("--serve-slots", type=int, default=2,
+                    help="launches in flight per catalog (continuous batching)")
     return ap.parse_args()
 
 
@@ -223,7 +225,7 @@ def serve_main(args):
         cats.append((w, c["k_max"], idx))
         print(f"[serve] catalog {nm}: n={c['n']} m={c['m']} d={c['d']} built in "
               f"{build[nm]['build_s']:.2f} s", file=sys.stderr, flush=True)
-    srv = Server(max_batch=args.serve_batch)
+    srv = Server(max_batch=args.serve_batch, slots=args.serve_slots)
     ids = [srv.add(idx) for _, _, idx in cats]
     rng = np.random.default_rng(12345)
 
@@ -312,7 +314,8 @@ def serve_main(args):
         "config": {"workload": "serving: catalogs (50k,10k,d50), (500k,50k,d100), (2M,100k,d200), "
                                "sigma 0.5, k_max 25; catalog uniform, query item from its P, "
                                "k ~ U{1..25}; Poisson arrivals",
-                   "max_batch": args.serve_batch, "lb_items": args.lb_items or "m",
+                   "max_batch": args.serve_batch, "slots_per_catalog": args.serve_slots,
+                   "lb_items": args.lb_items or "m",
                    "requests_per_load": args.serve_requests, "warmup": args.serve_warmup},
         "saturation_qps": sat_qps, "loads": loads, "catalogs": build,
         "server_device_bytes": srv.used_bytes(),

@@ -43,7 +43,8 @@ typedef enum {
     RK_E_KMAX = 2,   /* k > k_max of the index and auto_rebuild is off */
     RK_E_NOMEM = 3,  /* device allocation failed; nothing was created */
     RK_E_TRUNC = 4,  /* output capacity too small; counts hold true sizes */
-    RK_E_DEVICE = 5  /* HIP runtime error; see rk_last_error() */
+    RK_E_DEVICE = 5, /* HIP runtime error; see rk_last_error() */
+    RK_E_BUSY = 6    /* serving: the catalog's request queue is full */
 } rk_status;
 
 typedef enum {
@@ -234,20 +235,30 @@ const char *rk_last_error(void);
 /* ------------------------------------------------------------------------
  * Serving: the online phase (Algorithm 3; Theorem 2 bounds its cost per
  * query) under a stream of single-query requests over several resident
- * catalogs.  Every catalog has a batching thread and a HIP stream of its
- * own: the thread batches the catalog's pending requests continuously
- * (whatever is queued when its previous launch has finished, up to
- * max_batch) and runs them through the batched path of the catalog's index;
- * results come back to the host per request.  Catalogs run concurrently.
+ * catalogs, with continuous batching.  Every catalog has `slots` launch
+ * slots; a slot owns a HIP stream, a batch workspace for max_batch queries,
+ * query/result buffers and a thread.  A free slot takes whatever the
+ * catalog has queued (up to max_batch) and runs it through the batched path
+ * of the catalog's index; requests that arrive while that launch is on the
+ * device are taken by the next free slot, so their work overlaps on the
+ * device with the earlier launch (a small late request can finish before a
+ * large earlier batch).  Results come back to the host per request.
+ * Catalogs run concurrently.
  *
- * Catalogs are admitted by device-memory footprint: the index's own bytes
- * plus the batch workspace and the server's buffers for max_batch queries
- * must fit in what is left of hbm_budget, else RK_E_NOMEM.
+ * Admission by device-memory footprint: a catalog is admitted when its
+ * index's bytes plus, per slot, the batch workspace and buffers for
+ * max_batch queries fit in what is left of hbm_budget, else RK_E_NOMEM.  A
+ * request is admitted when its catalog's queue holds fewer than max_queue
+ * requests, else RK_E_BUSY; it needs no device memory of its own beyond its
+ * slot's, except when its batch's ids outgrow the slot's id buffer: the
+ * buffer grows within the budget, and when the budget does not allow it
+ * the batch runs in halves (a single result that cannot fit completes with
+ * status RK_E_NOMEM).
  *
  * A catalog's index is borrowed: it must outlive the server, and nothing
  * else may query it while the server runs.  Requests for different catalogs
- * never share a launch, so a catalog's results do not depend on the others'
- * traffic.  All functions are thread-safe.
+ * never share a launch, and a request's result set does not depend on what
+ * it was batched with.  All functions are thread-safe.
  * ---------------------------------------------------------------------- */
 typedef struct rk_server rk_server;
 
@@ -257,9 +268,12 @@ typedef struct {
     int32_t max_wait_us;  /* 0: launch as soon as the device is free;
                              > 0: a batch smaller than max_batch may wait up
                              to this long after its oldest request arrived */
-    int32_t reserved0;
+    int32_t slots;        /* 0 -> 2: launches in flight per catalog (1..16); an
+                             index whose batches run one query at a time
+                             (tiles too wide for the batched kernels) gets 1 */
     int64_t hbm_budget;   /* 0 -> 90% of the device memory free at creation */
-    int64_t reserved[6];
+    int64_t max_queue;    /* 0 -> 65536: queued requests per catalog */
+    int64_t reserved[5];
 } rk_server_opts;
 
 typedef struct {
@@ -281,12 +295,13 @@ rk_status rk_server_add_catalog(rk_server *s, rk_index *idx, int32_t *catalog);
 
 /* Queue one query (host vector of the catalog's d floats, copied) at k.
  * RK_E_INVAL: bad catalog, k < 1 or a non-finite value; RK_E_KMAX: k >
- * k_max (no rebuild while serving). */
+ * k_max (no rebuild while serving); RK_E_BUSY: the catalog's queue already
+ * holds max_queue requests (nothing is queued; retry later). */
 rk_status rk_server_submit(rk_server *s, int32_t catalog, const float *q, int32_t k,
                            int64_t tag);
 
 /* Queue n queries at once, with the checks of rk_server_submit (all or
- * nothing).  q[i] points to the d floats of query i's catalog.  arrival_ms
+ * nothing; RK_E_BUSY when some catalog's queue has no room for its share).  q[i] points to the d floats of query i's catalog.  arrival_ms
  * (or NULL: now) is each request's arrival on the server clock, the time its
  * latency counts from: an open-loop load generator that submits late passes
  * the scheduled times (later than now counts as now). */
@@ -306,13 +321,18 @@ double rk_server_now_ms(rk_server *s);
 int64_t rk_server_poll(rk_server *s, rk_completion *out, int64_t max_out, int32_t *ids,
                        int64_t ids_cap, int32_t wait_us);
 
-/* Requests submitted and not yet finished by the worker. */
+/* Requests submitted and not yet finished. */
 int64_t rk_server_inflight(rk_server *s);
+
+/* A catalog's queued requests (not yet taken by a slot) and its slots with
+ * a launch in flight. */
+rk_status rk_server_catalog_state(rk_server *s, int32_t catalog, int64_t *queued,
+                                  int32_t *running);
 
 /* Device bytes held by the admitted catalogs (indices, workspaces, buffers). */
 int64_t rk_server_used_bytes(rk_server *s);
 
-/* Finish the queued requests, stop the worker, release the server's own
+/* Finish the queued requests, stop the slots, release the server's own
  * buffers (not the indices).  Unpolled results are dropped. */
 void rk_server_free(rk_server *s);
 

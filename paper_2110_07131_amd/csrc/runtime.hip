@@ -2,6 +2,7 @@
 // index, validates arguments before any device work, sequences the build
 // (Algorithm 1) and query (Algorithms 2-3) kernels on the index's stream.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -59,6 +60,68 @@ double eps_bf16(int d) {
   return r + gamma_(d, 0x1p-53) + 16 * 0x1p-24;
 }
 
+// Device workspace of the batched path for chunks of up to qcap queries
+// (grown on demand).  An index owns one for its own calls; every serving slot
+// owns another, so that batches over one index can be in flight on several
+// streams at once.
+struct BatchWS {
+  int32_t qcap = 0;       // queries per chunk it is sized for
+  int64_t pair_cap = 0;
+  float *qn = nullptr, *qt = nullptr, *qn_s = nullptr, *pair_s = nullptr;
+  uint16_t* qb = nullptr;
+  unsigned long long* npairs = nullptr;
+  int32_t *perm = nullptr, *k_s = nullptr, *kofs_s = nullptr, *pair_u = nullptr,
+          *pair_j = nullptr, *ks_dev = nullptr;
+  // bounded table: chunked pair slots, per-block chunk lists
+  int32_t *pair_st = nullptr, *cfill = nullptr, *nchunks = nullptr, *bcnt = nullptr,
+          *bchunks = nullptr, *gl_i = nullptr, *gdone = nullptr;
+  float* gl_v = nullptr;
+  // users handed to the grouped pass and their pair slots
+  int32_t *sg_count = nullptr, *sg_users = nullptr, *sg_block = nullptr, *st_np = nullptr,
+          *st_pk = nullptr, *sg_key = nullptr, *sg_sorted = nullptr;
+  float *st_plo = nullptr, *st_ph = nullptr;
+  int32_t chunk_cap = 0, maxc = 0;
+  uint32_t* bits = nullptr;
+  unsigned long long* counts = nullptr;
+  uint8_t* all = nullptr;
+  int32_t* ks_pinned = nullptr;   // host staging of k values
+  int64_t ks_pinned_cap = 0;
+  hipEvent_t ks_done = nullptr;   // the last copy out of ks_pinned
+  std::vector<void*> dev;         // owned device buffers
+  int64_t bytes = 0;              // their size
+
+  template <typename T>
+  hipError_t alloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e == hipSuccess) {
+      dev.push_back((void*)*p);
+      bytes += (int64_t)(count * sizeof(T));
+    }
+    return e;
+  }
+  // Frees the device buffers (the pinned staging and its event stay).
+  void release() {
+    for (void* q : dev) (void)hipFree(q);
+    int32_t* kp = ks_pinned;
+    const int64_t kc = ks_pinned_cap;
+    hipEvent_t ke = ks_done;
+    *this = BatchWS();
+    ks_pinned = kp;
+    ks_pinned_cap = kc;
+    ks_done = ke;
+  }
+  void destroy() {
+    release();
+    if (ks_pinned) (void)hipHostFree(ks_pinned);
+    if (ks_done) (void)hipEventDestroy(ks_done);
+    ks_pinned = nullptr;
+    ks_pinned_cap = 0;
+    ks_done = nullptr;
+  }
+};
+
 }  // namespace
 
 struct rk_index {
@@ -94,41 +157,18 @@ struct rk_index {
   int64_t* count_host = nullptr;
   int32_t* ids_host_dev = nullptr;
   int64_t* count_host_dev = nullptr;
-  // batched-query workspace (grown on demand)
-  struct {
-    int32_t qcap = 0;       // queries per chunk it is sized for
-    int64_t pair_cap = 0;
-    float *qn = nullptr, *qt = nullptr, *qn_s = nullptr, *pair_s = nullptr;
-    uint16_t* qb = nullptr;
-    unsigned long long* npairs = nullptr;
-    int32_t *perm = nullptr, *k_s = nullptr, *kofs_s = nullptr, *pair_u = nullptr,
-            *pair_j = nullptr, *ks_dev = nullptr;
-    // bounded table: chunked pair slots, per-block chunk lists
-    int32_t *pair_st = nullptr, *cfill = nullptr, *nchunks = nullptr, *bcnt = nullptr,
-            *bchunks = nullptr, *gl_i = nullptr, *gdone = nullptr;
-    float* gl_v = nullptr;
-    // users handed to the grouped pass and their pair slots
-    int32_t *sg_count = nullptr, *sg_users = nullptr, *sg_block = nullptr, *st_np = nullptr,
-            *st_pk = nullptr, *sg_key = nullptr, *sg_sorted = nullptr;
-    float *st_plo = nullptr, *st_ph = nullptr;
-    int32_t chunk_cap = 0, maxc = 0;
-    uint32_t* bits = nullptr;
-    unsigned long long* counts = nullptr;
-    uint8_t* all = nullptr;
-    int32_t* ks_pinned = nullptr;   // host staging of k values
-    int64_t ks_pinned_cap = 0;
-    hipEvent_t ks_done = nullptr;   // the last copy out of ks_pinned
-  } bw;
+  // batched-query workspace of the index's own calls (grown on demand)
+  BatchWS bw;
   // build statistics
   double build_ms = 0;
   int64_t cand_total = 0, cand_ovf = 0, rebuilds = 0;
-  int64_t queries = 0;
+  std::atomic<int64_t> queries{0};
 
   ~rk_index() {
     if (device >= 0) (void)hipSetDevice(device);
     if (stream) (void)hipStreamSynchronize(stream);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-    if (bw.ks_done) (void)hipEventDestroy(bw.ks_done);
+    bw.destroy();
     for (auto& b : dbufs) (void)hipFree(b.first);
     for (void* p : hbufs) (void)hipHostFree(p);
     if (stream) (void)hipStreamDestroy(stream);
@@ -430,8 +470,8 @@ struct Timer {
   hipStream_t s;
   int cls;
   hipEvent_t e0 = nullptr;
-  Timer(rk_index* h_, hipStream_t s_, int c) : h(h_), s(s_), cls(c) {
-    if (!h->timing || h->ev_next + 2 > h->ev_pool.size()) return;
+  Timer(rk_index* h_, hipStream_t s_, int c, bool on = true) : h(h_), s(s_), cls(c) {
+    if (!on || !h->timing || h->ev_next + 2 > h->ev_pool.size()) return;
     e0 = h->ev_pool[h->ev_next++];
     (void)hipEventRecord(e0, s);
   }
@@ -554,69 +594,56 @@ int32_t batch_chunk(const rk_index* h, int64_t nq) {
   return (int32_t)std::max<int64_t>(1, c);
 }
 
-rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
-  auto& b = h->bw;
+rk_status ensure_batch_ws(rk_index* h, BatchWS& b, int32_t chunk, hipStream_t s) {
   if (b.qcap >= chunk) return RK_OK;
-  HIPTRY(hipStreamSynchronize(h->stream));
-  for (void* p : {(void*)b.qn, (void*)b.qt, (void*)b.qn_s, (void*)b.pair_s, (void*)b.qb,
-                  (void*)b.perm, (void*)b.k_s, (void*)b.kofs_s, (void*)b.npairs, (void*)b.pair_u,
-                  (void*)b.pair_j,
-                  (void*)b.ks_dev, (void*)b.bits, (void*)b.counts, (void*)b.all,
-                  (void*)b.pair_st, (void*)b.cfill, (void*)b.nchunks, (void*)b.bcnt,
-                  (void*)b.bchunks, (void*)b.gl_v, (void*)b.gl_i, (void*)b.gdone,
-                  (void*)b.sg_count, (void*)b.sg_users, (void*)b.sg_block, (void*)b.st_np,
-                  (void*)b.st_pk, (void*)b.st_plo, (void*)b.st_ph, (void*)b.sg_key,
-                  (void*)b.sg_sorted})
-    if (p) h->dfree(p);
-  b.pair_st = b.cfill = b.nchunks = b.bcnt = b.bchunks = b.gl_i = b.gdone = nullptr;
-  b.sg_count = b.sg_users = b.sg_block = b.st_np = b.st_pk = b.sg_key = b.sg_sorted = nullptr;
-  b.gl_v = b.st_plo = b.st_ph = nullptr;
+  // earlier calls may still use the buffers, on this stream or another
+  HIPTRY(hipDeviceSynchronize());
+  b.release();
   const DevIndex& ix = h->ix;
   const BatchSizes z = batch_sizes(h, chunk);
   const int64_t cp = round_up(chunk, TILE), W = bitmap_words(ix.n);
   const int64_t pc = z.pc;
-  b.qcap = 0;
-  HIPTRY(h->dalloc(&b.qn, chunk));
-  HIPTRY(h->dalloc(&b.perm, chunk));
-  HIPTRY(h->dalloc(&b.qt, cp * (ix.d + (ix.d & 1))));
-  if (ix.bf16) HIPTRY(h->dalloc(&b.qb, cp * ix.d16));
-  HIPTRY(h->dalloc(&b.qn_s, cp));
-  HIPTRY(h->dalloc(&b.k_s, cp));
-  HIPTRY(h->dalloc(&b.kofs_s, cp));
-  HIPTRY(h->dalloc(&b.bits, (size_t)chunk * std::max<int64_t>(W, 1)));
-  HIPTRY(h->dalloc(&b.counts, chunk));
-  HIPTRY(h->dalloc(&b.all, chunk));
-  HIPTRY(h->dalloc(&b.npairs, 1));
-  HIPTRY(h->dalloc(&b.pair_u, pc));
-  HIPTRY(h->dalloc(&b.pair_j, pc));
-  HIPTRY(h->dalloc(&b.pair_s, pc));
-  HIPTRY(h->dalloc(&b.ks_dev, chunk));
+  HIPTRY(b.alloc(&b.qn, chunk));
+  HIPTRY(b.alloc(&b.perm, chunk));
+  HIPTRY(b.alloc(&b.qt, cp * (ix.d + (ix.d & 1))));
+  if (ix.bf16) HIPTRY(b.alloc(&b.qb, cp * ix.d16));
+  HIPTRY(b.alloc(&b.qn_s, cp));
+  HIPTRY(b.alloc(&b.k_s, cp));
+  HIPTRY(b.alloc(&b.kofs_s, cp));
+  HIPTRY(b.alloc(&b.bits, (size_t)chunk * std::max<int64_t>(W, 1)));
+  HIPTRY(b.alloc(&b.counts, chunk));
+  HIPTRY(b.alloc(&b.all, chunk));
+  HIPTRY(b.alloc(&b.npairs, 1));
+  HIPTRY(b.alloc(&b.pair_u, pc));
+  HIPTRY(b.alloc(&b.pair_j, pc));
+  HIPTRY(b.alloc(&b.pair_s, pc));
+  HIPTRY(b.alloc(&b.ks_dev, chunk));
   if (!ix.exact) {
     b.chunk_cap = (int32_t)z.chunk_cap;
     b.maxc = (int32_t)z.maxc;
-    HIPTRY(h->dalloc(&b.pair_st, std::max<int64_t>(pc, 1)));
-    HIPTRY(h->dalloc(&b.cfill, std::max<int64_t>(b.chunk_cap, 1)));
-    HIPTRY(h->dalloc(&b.nchunks, 1));
-    HIPTRY(h->dalloc(&b.bcnt, std::max<int64_t>(ix.nB, 1)));
-    HIPTRY(h->dalloc(&b.bchunks, (int64_t)std::max<int64_t>(ix.nB, 1) * b.maxc));
+    HIPTRY(b.alloc(&b.pair_st, std::max<int64_t>(pc, 1)));
+    HIPTRY(b.alloc(&b.cfill, std::max<int64_t>(b.chunk_cap, 1)));
+    HIPTRY(b.alloc(&b.nchunks, 1));
+    HIPTRY(b.alloc(&b.bcnt, std::max<int64_t>(ix.nB, 1)));
+    HIPTRY(b.alloc(&b.bchunks, (int64_t)std::max<int64_t>(ix.nB, 1) * b.maxc));
     const int64_t nl = std::max<int64_t>(ix.n_pad, 1) * bscan_list_len(ix.kmax);
-    HIPTRY(h->dalloc(&b.gl_v, nl));
-    HIPTRY(h->dalloc(&b.gl_i, nl));
-    HIPTRY(h->dalloc(&b.gdone, std::max<int64_t>(ix.n_pad, 1)));
+    HIPTRY(b.alloc(&b.gl_v, nl));
+    HIPTRY(b.alloc(&b.gl_i, nl));
+    HIPTRY(b.alloc(&b.gdone, std::max<int64_t>(ix.n_pad, 1)));
     const int64_t np1 = std::max<int64_t>(ix.n_pad, 1);
-    HIPTRY(h->dalloc(&b.sg_count, 2));
-    HIPTRY(h->dalloc(&b.sg_users, 2 * np1));
-    HIPTRY(h->dalloc(&b.sg_block, std::max<int64_t>(ix.nB, 1)));
-    HIPTRY(h->dalloc(&b.st_np, np1));
-    HIPTRY(h->dalloc(&b.st_pk, np1 * kUserPairs));
-    HIPTRY(h->dalloc(&b.st_plo, np1 * kUserPairs));
-    HIPTRY(h->dalloc(&b.st_ph, np1 * kUserPairs));
-    HIPTRY(h->dalloc(&b.sg_key, np1));
-    HIPTRY(h->dalloc(&b.sg_sorted, np1));
+    HIPTRY(b.alloc(&b.sg_count, 2));
+    HIPTRY(b.alloc(&b.sg_users, 2 * np1));
+    HIPTRY(b.alloc(&b.sg_block, std::max<int64_t>(ix.nB, 1)));
+    HIPTRY(b.alloc(&b.st_np, np1));
+    HIPTRY(b.alloc(&b.st_pk, np1 * kUserPairs));
+    HIPTRY(b.alloc(&b.st_plo, np1 * kUserPairs));
+    HIPTRY(b.alloc(&b.st_ph, np1 * kUserPairs));
+    HIPTRY(b.alloc(&b.sg_key, np1));
+    HIPTRY(b.alloc(&b.sg_sorted, np1));
   }
-  HIPTRY(hipMemsetAsync(b.bits, 0, (size_t)chunk * std::max<int64_t>(W, 1) * 4, h->stream));
-  HIPTRY(hipMemsetAsync(b.counts, 0, (size_t)chunk * 8, h->stream));
-  HIPTRY(hipStreamSynchronize(h->stream));
+  HIPTRY(hipMemsetAsync(b.bits, 0, (size_t)chunk * std::max<int64_t>(W, 1) * 4, s));
+  HIPTRY(hipMemsetAsync(b.counts, 0, (size_t)chunk * 8, s));
+  HIPTRY(hipStreamSynchronize(s));
   b.qcap = chunk;
   b.pair_cap = pc;
   return RK_OK;
@@ -624,19 +651,14 @@ rk_status ensure_batch_ws(rk_index* h, int32_t chunk) {
 
 // Stage k values in pinned memory (guarded by an event so a previous copy
 // out of it has finished) and copy them to the device.
-rk_status stage_ks(rk_index* h, const int32_t* ks, int64_t nq, int32_t* dst, hipStream_t s) {
-  auto& b = h->bw;
+rk_status stage_ks(BatchWS& b, const int32_t* ks, int64_t nq, int32_t* dst, hipStream_t s) {
   if (!b.ks_done) HIPTRY(hipEventCreateWithFlags(&b.ks_done, hipEventDisableTiming));
   HIPTRY(hipEventSynchronize(b.ks_done));
   if (b.ks_pinned_cap < nq) {
-    if (b.ks_pinned) {
-      (void)hipHostFree(b.ks_pinned);
-      h->hbufs.erase(std::find(h->hbufs.begin(), h->hbufs.end(), (void*)b.ks_pinned));
-    }
+    if (b.ks_pinned) (void)hipHostFree(b.ks_pinned);
     b.ks_pinned = nullptr;
     b.ks_pinned_cap = 0;
     HIPTRY(hipHostMalloc((void**)&b.ks_pinned, nq * sizeof(int32_t), hipHostMallocDefault));
-    h->hbufs.push_back(b.ks_pinned);
     b.ks_pinned_cap = nq;
   }
   std::memcpy(b.ks_pinned, ks, nq * sizeof(int32_t));
@@ -645,15 +667,25 @@ rk_status stage_ks(rk_index* h, const int32_t* ks, int64_t nq, int32_t* dst, hip
   return RK_OK;
 }
 
-rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int32_t* ks,
-                        int64_t* offs, int32_t* ids, int64_t cap, hipStream_t s) {
+// The batch path cannot run this index's tiles (too wide for the filter's or
+// the scan's LDS): batch calls go one query at a time through the index's
+// single-query workspace.
+bool batch_one_at_a_time(const DevIndex& ix) {
+  const size_t tile_bytes = ix.bf16 ? (size_t)ix.d16 * TILE * 2 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
+  return bfilter_lds_bytes(ix) > kMaxLds || tile_bytes > bfilter_max_tile_bytes() ||
+         (!ix.exact && !bscan_fits(ix));
+}
+
+// Enqueues a batch on stream s with workspace b (per-kernel event timing
+// only when `timed`, for the index's own calls).
+rk_status batch_enqueue(rk_index* h, BatchWS& b, const float* qs_dev, int64_t nq,
+                        const int32_t* ks, int64_t* offs, int32_t* ids, int64_t cap,
+                        hipStream_t s, bool timed) {
   const DevIndex& ix = h->ix;
   launch_set_i64(offs, 0, s);
   HIPTRY(hipGetLastError());
   if (nq == 0) return RK_OK;
-  const size_t tile_bytes = ix.bf16 ? (size_t)ix.d16 * TILE * 2 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
-  if (bfilter_lds_bytes(ix) > kMaxLds || tile_bytes > bfilter_max_tile_bytes() ||
-      (!ix.exact && !bscan_fits(ix))) {
+  if (batch_one_at_a_time(ix)) {
     // too wide for the block-resident batched filter: one query at a time
     for (int64_t i = 0; i < nq; ++i) {
       rk_status st = enqueue_query(h, qs_dev + i * ix.d, ks[i], ids, cap, offs + i, offs + i + 1,
@@ -664,12 +696,11 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
   }
   const int64_t W = bitmap_words(ix.n);
   const int32_t chunk = batch_chunk(h, nq);
-  rk_status st = ensure_batch_ws(h, chunk);
+  rk_status st = ensure_batch_ws(h, b, chunk, s);
   if (st != RK_OK) return st;
-  auto& b = h->bw;
   for (int64_t c0 = 0; c0 < nq; c0 += chunk) {
     const int32_t nc = (int32_t)std::min<int64_t>(chunk, nq - c0);
-    if ((st = stage_ks(h, ks + c0, nc, b.ks_dev, s)) != RK_OK) return st;
+    if ((st = stage_ks(b, ks + c0, nc, b.ks_dev, s)) != RK_OK) return st;
     BatchView bv{};
     bv.qs = qs_dev + c0 * ix.d;
     bv.qn = b.qn; bv.perm = b.perm; bv.qt = b.qt; bv.qb = b.qb;
@@ -687,10 +718,10 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
     bv.carry_out = c0 + nc < nq;
     if (c0 == 0 && bv.carry_out) launch_bscan_reset(ix, bv, s);  // the scan state is per call
     bv.ctr = h->counting ? h->ctr_dev : nullptr;
-    { Timer t(h, s, K_BPREP); launch_bprep(ix, bv, b.ks_dev, nc, s); }
-    { Timer t(h, s, K_BFILTER); launch_bfilter(ix, bv, s); }
-    { Timer t(h, s, K_BPAIRS); launch_bpairs(ix, bv, s); }
-    { Timer t(h, s, K_BASSEMBLE); launch_bassemble(bv, nc, offs + c0, offs + c0, ids, cap, s); }
+    { Timer t(h, s, K_BPREP, timed); launch_bprep(ix, bv, b.ks_dev, nc, s); }
+    { Timer t(h, s, K_BFILTER, timed); launch_bfilter(ix, bv, s); }
+    { Timer t(h, s, K_BPAIRS, timed); launch_bpairs(ix, bv, s); }
+    { Timer t(h, s, K_BASSEMBLE, timed); launch_bassemble(bv, nc, offs + c0, offs + c0, ids, cap, s); }
     HIPTRY(hipGetLastError());
     h->queries += nc;
   }
@@ -701,6 +732,15 @@ rk_status batch_enqueue(rk_index* h, const float* qs_dev, int64_t nq, const int3
 
 // ===========================================================================
 // Serving: continuous batching over resident catalogs (rk_server_*).
+//
+// Every catalog has `slots` launch slots.  A slot owns a HIP stream, a
+// batch workspace sized for max_batch queries, query/offset/id buffers and a
+// thread.  A free slot takes whatever the catalog has queued (up to
+// max_batch), launches it on its stream and waits for it; requests that
+// arrive meanwhile are taken by the next free slot, so their work runs on
+// the device while the earlier launch is still there.  Device memory is
+// reserved per slot when the catalog is admitted, so requests never allocate
+// workspace; only the id buffers of a slot grow, within the budget.
 namespace {
 
 struct ServerReq {
@@ -715,10 +755,8 @@ struct ServerDone {
   std::vector<int32_t> ids;
 };
 
-struct ServerCatalog {
-  rk_index* idx = nullptr;
-  int32_t d = 0;
-  std::deque<ServerReq> queue;
+struct ServerSlot {
+  BatchWS ws;
   hipStream_t stream = nullptr;
   float* q_dev = nullptr;
   int64_t* offs_dev = nullptr;
@@ -727,16 +765,44 @@ struct ServerCatalog {
   float* q_pin = nullptr;
   int64_t* offs_pin = nullptr;
   int32_t* ids_pin = nullptr;
-  int64_t bytes = 0;  // device bytes charged to the budget
-  std::condition_variable cv;  // requests queued (or the server stops)
-  std::thread worker;          // this catalog's batching thread
+  std::thread worker;
+};
+
+// Launch-time estimates per batch-size bucket (ceil(log2(nq)), 0..15).
+constexpr int kSizeBuckets = 16;
+inline int size_bucket(int64_t nq) {
+  int b = 0;
+  while (b < kSizeBuckets - 1 && (int64_t(1) << b) < nq) ++b;
+  return b;
+}
+
+struct ServerCatalog {
+  rk_index* idx = nullptr;
+  int32_t d = 0;
+  std::deque<ServerReq> queue;
+  std::vector<ServerSlot*> slots;
+  int32_t running = 0;          // slots with a launch in flight
+  std::vector<double> starts;   // start of each running launch
+  int64_t bytes = 0;            // device bytes charged to the budget
+  double est_ms[kSizeBuckets];  // moving average of launch time by batch size (< 0: none yet)
+  std::condition_variable cv;   // requests queued, a launch ended, or the server stops
+  ServerCatalog() { for (double& e : est_ms) e = -1.0; }
+  // Estimated time of a launch of nq queries: the smallest bucket at or
+  // above nq's with a measurement (< 0 when there is none).
+  double estimate(int64_t nq) const {
+    for (int b = size_bucket(nq); b < kSizeBuckets; ++b)
+      if (est_ms[b] >= 0) return est_ms[b];
+    return -1.0;
+  }
 };
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-void free_catalog_buffers(ServerCatalog* c) {
+void free_slot_buffers(ServerSlot* c) {
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  c->ws.destroy();
   if (c->q_dev) (void)hipFree(c->q_dev);
   if (c->offs_dev) (void)hipFree(c->offs_dev);
   if (c->ids_dev) (void)hipFree(c->ids_dev);
@@ -753,7 +819,7 @@ void free_catalog_buffers(ServerCatalog* c) {
   c->stream = nullptr;
 }
 
-hipError_t alloc_ids(ServerCatalog* c, int64_t cap) {
+hipError_t alloc_ids(ServerSlot* c, int64_t cap) {
   if (c->ids_dev) (void)hipFree(c->ids_dev);
   if (c->ids_pin) (void)hipHostFree(c->ids_pin);
   c->ids_dev = nullptr;
@@ -779,41 +845,34 @@ struct rk_server {
   int64_t budget = 0;
   bool stop = false;
 
-  // One launch for the queued requests of catalog c, results to the host.
-  void run_batch(int32_t ci, ServerCatalog* c, std::vector<ServerReq>& batch) {
-    const int64_t nq = (int64_t)batch.size();
-    const int d = c->d;
-    std::vector<int32_t> ks(nq);
-    for (int64_t i = 0; i < nq; ++i) {
-      std::memcpy(c->q_pin + i * d, batch[i].q.data(), d * sizeof(float));
-      ks[i] = batch[i].k;
-    }
-    rk_status st = RK_OK;
-    int64_t total = 0;
-    hipError_t e = hipMemcpyAsync(c->q_dev, c->q_pin, nq * d * sizeof(float), hipMemcpyHostToDevice, c->stream);
-    for (int attempt = 0; attempt < 2 && e == hipSuccess; ++attempt) {
-      st = batch_enqueue(c->idx, c->q_dev, nq, ks.data(), c->offs_dev, c->ids_dev, c->ids_cap, c->stream);
-      if (st != RK_OK) break;
-      e = hipMemcpyAsync(c->offs_pin, c->offs_dev, (nq + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-      if (e != hipSuccess) break;
-      total = c->offs_pin[nq];
-      if (total <= c->ids_cap) break;
-      // more results than the id buffers hold: grow them, run the batch again
-      const int64_t old = c->ids_cap;
-      e = alloc_ids(c, total + total / 4 + 1024);
+  // Grows slot c's id buffers to hold `want` ids if the budget allows.
+  bool grow_ids(ServerCatalog* cat, ServerSlot* c, int64_t want) {
+    const int64_t cap = want + want / 4 + 1024;
+    const int64_t extra = (cap - c->ids_cap) * (int64_t)sizeof(int32_t);
+    {
       std::lock_guard<std::mutex> lk(mu);
-      used += (c->ids_cap - old) * (int64_t)sizeof(int32_t);
-      c->bytes += (c->ids_cap - old) * (int64_t)sizeof(int32_t);
+      if (used + extra > budget) return false;
+      used += extra;
+      cat->bytes += extra;
     }
-    if (e == hipSuccess && st == RK_OK && total > 0) {
-      e = hipMemcpyAsync(c->ids_pin, c->ids_dev, total * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    const int64_t old = c->ids_cap;
+    if (alloc_ids(c, cap) == hipSuccess) return true;
+    // the old buffers are gone too: take back what they held, try them again
+    std::lock_guard<std::mutex> lk(mu);
+    used -= extra;
+    cat->bytes -= extra;
+    if (alloc_ids(c, old) != hipSuccess) {
+      used -= old * (int64_t)sizeof(int32_t);
+      cat->bytes -= old * (int64_t)sizeof(int32_t);
     }
-    if (st == RK_OK && e != hipSuccess) st = e == hipErrorOutOfMemory ? RK_E_NOMEM : RK_E_DEVICE;
+    return false;
+  }
+
+  void finish(int32_t ci, const std::vector<ServerReq>& batch, int64_t lo, int64_t hi,
+              rk_status st, const ServerSlot* c) {
     const double t_done = ms_since(t0);
     std::lock_guard<std::mutex> lk(mu);
-    for (int64_t i = 0; i < nq; ++i) {
+    for (int64_t i = lo; i < hi; ++i) {
       ServerDone dn;
       dn.c.tag = batch[i].tag;
       dn.c.catalog = ci;
@@ -821,46 +880,117 @@ struct rk_server {
       dn.c.submit_ms = batch[i].t_submit;
       dn.c.done_ms = t_done;
       if (st == RK_OK) {
-        const int64_t a = c->offs_pin[i], b = c->offs_pin[i + 1];
+        const int64_t a = c->offs_pin[i - lo], b = c->offs_pin[i - lo + 1];
         dn.c.count = b - a;
         dn.ids.assign(c->ids_pin + a, c->ids_pin + b);
       }
       done.push_back(std::move(dn));
     }
-    inflight -= nq;
+    inflight -= hi - lo;
     cv_done.notify_all();
   }
 
-  // Batching thread of catalog ci: every catalog has its own thread and
-  // stream, so catalogs run concurrently and a small catalog's requests do
-  // not wait behind a large catalog's launch.
-  void loop(int32_t ci, ServerCatalog* c) {
+  // Runs requests [lo, hi) of a batch on slot c and hands their results over.
+  // A launch whose ids do not fit the slot's buffers grows them within the
+  // budget and runs again; when the budget does not allow it, the range is
+  // run in halves (a single request that cannot fit fails with RK_E_NOMEM).
+  void run_range(int32_t ci, ServerCatalog* cat, ServerSlot* c, const std::vector<ServerReq>& batch,
+                 int64_t lo, int64_t hi) {
+    const int64_t nq = hi - lo;
+    const int d = cat->d;
+    std::vector<int32_t> ks(nq);
+    for (int64_t i = 0; i < nq; ++i) {
+      std::memcpy(c->q_pin + i * d, batch[lo + i].q.data(), d * sizeof(float));
+      ks[i] = batch[lo + i].k;
+    }
+    rk_status st = RK_OK;
+    int64_t total = 0;
+    hipError_t e = hipMemcpyAsync(c->q_dev, c->q_pin, nq * d * sizeof(float), hipMemcpyHostToDevice, c->stream);
+    for (int attempt = 0; attempt < 2 && e == hipSuccess; ++attempt) {
+      st = batch_enqueue(cat->idx, c->ws, c->q_dev, nq, ks.data(), c->offs_dev, c->ids_dev, c->ids_cap,
+                         c->stream, false);
+      if (st != RK_OK) break;
+      e = hipMemcpyAsync(c->offs_pin, c->offs_dev, (nq + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) break;
+      total = c->offs_pin[nq];
+      if (total <= c->ids_cap) break;
+      if (attempt == 1 || !grow_ids(cat, c, total)) {
+        if (nq == 1) {
+          st = fail(RK_E_NOMEM, "serving: a result does not fit the device budget");
+          break;
+        }
+        const int64_t mid = lo + nq / 2;
+        run_range(ci, cat, c, batch, lo, mid);
+        run_range(ci, cat, c, batch, mid, hi);
+        return;
+      }
+    }
+    if (e == hipSuccess && st == RK_OK && total > 0) {
+      e = hipMemcpyAsync(c->ids_pin, c->ids_dev, total * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (st == RK_OK && e != hipSuccess) st = e == hipErrorOutOfMemory ? RK_E_NOMEM : RK_E_DEVICE;
+    finish(ci, batch, lo, hi, st, c);
+  }
+
+  // Thread of one slot of catalog ci.  With no launch of the catalog on the
+  // device it takes the queued requests at once.  While another slot's
+  // launch runs, it joins in only when that launch has already run at least
+  // twice as long as the queued requests are expected to take on their own
+  // (measured launch times by batch size): a request arriving early in a
+  // long launch then finishes long before it, while launches of similar
+  // size do not split the device between them (each would finish later).
+  void loop(int32_t ci, ServerCatalog* cat, ServerSlot* c) {
     (void)hipSetDevice(opts.device);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-      c->cv.wait(lk, [&] { return stop || !c->queue.empty(); });
-      if (c->queue.empty()) {
+      cat->cv.wait(lk, [&] { return stop || !cat->queue.empty(); });
+      if (cat->queue.empty()) {
         if (stop) break;
         continue;
       }
       if (opts.max_wait_us > 0) {
-        const double deadline = c->queue.front().t_submit + opts.max_wait_us / 1000.0;
-        while (!stop && (int64_t)c->queue.size() < opts.max_batch) {
+        const double deadline = cat->queue.front().t_submit + opts.max_wait_us / 1000.0;
+        while (!stop && (int64_t)cat->queue.size() < opts.max_batch) {
           const double left = deadline - ms_since(t0);
           if (left <= 0) break;
-          c->cv.wait_for(lk, std::chrono::duration<double, std::milli>(left));
+          cat->cv.wait_for(lk, std::chrono::duration<double, std::milli>(left));
+        }
+        if (cat->queue.empty()) continue;  // another slot took them
+      }
+      if (cat->running > 0 && !stop) {
+        const int64_t want = std::min<int64_t>((int64_t)cat->queue.size(), opts.max_batch);
+        const double tb = cat->estimate(want);
+        const double elapsed = ms_since(t0) - *std::min_element(cat->starts.begin(), cat->starts.end());
+        if (tb < 0) {                       // no estimate yet: wait for the launch to end
+          cat->cv.wait(lk);
+          continue;
+        }
+        if (elapsed < 2 * tb) {
+          cat->cv.wait_for(lk, std::chrono::duration<double, std::milli>(2 * tb - elapsed));
+          continue;
         }
       }
-      const int64_t nb = std::min<int64_t>((int64_t)c->queue.size(), opts.max_batch);
+      const int64_t nb = std::min<int64_t>((int64_t)cat->queue.size(), opts.max_batch);
       std::vector<ServerReq> batch;
       batch.reserve(nb);
       for (int64_t i = 0; i < nb; ++i) {
-        batch.push_back(std::move(c->queue.front()));
-        c->queue.pop_front();
+        batch.push_back(std::move(cat->queue.front()));
+        cat->queue.pop_front();
       }
+      ++cat->running;
+      const double started = ms_since(t0);
+      cat->starts.push_back(started);
       lk.unlock();
-      run_batch(ci, c, batch);
+      run_range(ci, cat, c, batch, 0, nb);
       lk.lock();
+      const double took = ms_since(t0) - started;
+      cat->starts.erase(std::find(cat->starts.begin(), cat->starts.end(), started));
+      --cat->running;
+      double& e = cat->est_ms[size_bucket(nb)];
+      e = e < 0 ? took : 0.7 * e + 0.3 * took;
+      cat->cv.notify_all();  // slots waiting for this launch re-decide
     }
   }
 
@@ -869,14 +999,17 @@ struct rk_server {
       std::lock_guard<std::mutex> lk(mu);
       stop = true;
     }
-    for (ServerCatalog* c : cats) c->cv.notify_all();
-    for (ServerCatalog* c : cats)
-      if (c->worker.joinable()) c->worker.join();
+    for (ServerCatalog* cat : cats) cat->cv.notify_all();
+    for (ServerCatalog* cat : cats)
+      for (ServerSlot* c : cat->slots)
+        if (c->worker.joinable()) c->worker.join();
     (void)hipSetDevice(opts.device);
-    for (ServerCatalog* c : cats) {
-      if (c->stream) (void)hipStreamSynchronize(c->stream);
-      free_catalog_buffers(c);
-      delete c;
+    for (ServerCatalog* cat : cats) {
+      for (ServerSlot* c : cat->slots) {
+        free_slot_buffers(c);
+        delete c;
+      }
+      delete cat;
     }
   }
 };
@@ -997,7 +1130,7 @@ rk_status rk_reverse_kmips_batch_dev(rk_index* h, const float* qs_dev, int64_t n
   if (st != RK_OK) return st;
   HIPTRY(hipSetDevice(h->device));
   hipStream_t s = stream ? (hipStream_t)stream : h->stream;
-  return batch_enqueue(h, qs_dev, nq, ks, offsets_dev, ids_dev, cap, s);
+  return batch_enqueue(h, h->bw, qs_dev, nq, ks, offsets_dev, ids_dev, cap, s, true);
 }
 
 rk_status rk_reverse_kmips_batch(rk_index* h, const float* qs, int64_t nq, const int32_t* ks,
@@ -1087,7 +1220,7 @@ rk_status rk_index_stats(const rk_index* hc, rk_stats* o) {
   const DevIndex& ix = h->ix;
   o->n = ix.n; o->m = ix.m; o->d = ix.d; o->k_max = ix.kmax; o->lb_items = ix.lb_items;
   o->block_size = TILE; o->n_blocks = ix.nB; o->precision = ix.bf16 ? RK_BF16 : RK_FP32;
-  o->footprint_bytes = (int64_t)h->footprint;
+  o->footprint_bytes = (int64_t)h->footprint + h->bw.bytes;
   o->build_ms = h->build_ms;
   o->build_cand_total = h->cand_total;
   o->build_cand_overflow_users = h->cand_ovf;
@@ -1156,6 +1289,8 @@ void rk_server_opts_default(rk_server_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
   o->max_batch = 1024;
+  o->slots = 2;
+  o->max_queue = 1 << 16;
 }
 
 rk_status rk_server_create(const rk_server_opts* opts, rk_server** out) {
@@ -1165,8 +1300,11 @@ rk_status rk_server_create(const rk_server_opts* opts, rk_server** out) {
   rk_server_opts_default(&o);
   if (opts) o = *opts;
   if (o.max_batch == 0) o.max_batch = 1024;
-  if (o.max_batch < 0 || o.max_wait_us < 0 || o.hbm_budget < 0)
-    return fail(RK_E_INVAL, "max_batch, max_wait_us and hbm_budget must be >= 0");
+  if (o.slots == 0) o.slots = 2;
+  if (o.max_queue == 0) o.max_queue = 1 << 16;
+  if (o.max_batch < 0 || o.max_wait_us < 0 || o.hbm_budget < 0 || o.slots < 0 || o.max_queue < 0)
+    return fail(RK_E_INVAL, "max_batch, max_wait_us, slots, max_queue and hbm_budget must be >= 0");
+  if (o.slots > 16) return fail(RK_E_INVAL, "slots must be at most 16");
   int ndev = 0;
   HIPTRY(hipGetDeviceCount(&ndev));
   if (o.device < 0 || o.device >= ndev) return fail(RK_E_INVAL, "no such device");
@@ -1196,43 +1334,54 @@ rk_status rk_server_add_catalog(rk_server* s, rk_index* h, int32_t* catalog) {
   HIPTRY(hipSetDevice(s->opts.device));
   const int64_t B = s->opts.max_batch, d = h->ix.d;
   const int32_t chunk = batch_chunk(h, B);
-  const int64_t ws = h->bw.qcap >= chunk ? 0 : batch_sizes(h, chunk).bytes;
+  // an index whose batches go one query at a time shares its single-query
+  // workspace between launches: one slot
+  const int32_t nslots = batch_one_at_a_time(h->ix) ? 1 : s->opts.slots;
+  const int64_t ws = batch_sizes(h, chunk).bytes;
   const int64_t ids0 = B * 64;
   const int64_t bufs = B * d * 4 + (B + 1) * 8 + ids0 * 4;
-  const int64_t need = (int64_t)h->footprint + ws + bufs;
+  const int64_t need = (int64_t)h->footprint + h->bw.bytes + nslots * (ws + bufs);
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->used + need > s->budget)
-      return fail(RK_E_NOMEM, "admission: the catalog needs " + std::to_string(need) + " device bytes, " +
+      return fail(RK_E_NOMEM, "admission: the catalog needs " + std::to_string(need) + " device bytes (" +
+                                  std::to_string(nslots) + " slots), " +
                                   std::to_string(s->budget - s->used) + " of the budget are left");
     s->used += need;
   }
-  auto c = new ServerCatalog();
-  c->idx = h;
-  c->d = (int32_t)d;
-  c->bytes = need;
+  auto cat = new ServerCatalog();
+  cat->idx = h;
+  cat->d = (int32_t)d;
+  cat->bytes = need;
   auto undo = [&](rk_status st) {
-    free_catalog_buffers(c);
-    delete c;
+    for (ServerSlot* c : cat->slots) {
+      free_slot_buffers(c);
+      delete c;
+    }
+    delete cat;
     std::lock_guard<std::mutex> lk(s->mu);
     s->used -= need;
     return st;
   };
-  rk_status st = ensure_batch_ws(h, chunk);
-  if (st != RK_OK) return undo(st);
-  hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipMalloc((void**)&c->q_dev, std::max<int64_t>(B * d, 1) * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc((void**)&c->offs_dev, (B + 1) * sizeof(int64_t));
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->q_pin, std::max<int64_t>(B * d, 1) * sizeof(float), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->offs_pin, (B + 1) * sizeof(int64_t), hipHostMallocDefault);
-  if (e == hipSuccess) e = alloc_ids(c, ids0);
-  if (e != hipSuccess)
-    return undo(fail(e == hipErrorOutOfMemory ? RK_E_NOMEM : RK_E_DEVICE, hipGetErrorString(e)));
+  for (int32_t i = 0; i < nslots; ++i) {
+    auto c = new ServerSlot();
+    cat->slots.push_back(c);
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->q_dev, std::max<int64_t>(B * d, 1) * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->offs_dev, (B + 1) * sizeof(int64_t));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->q_pin, std::max<int64_t>(B * d, 1) * sizeof(float), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->offs_pin, (B + 1) * sizeof(int64_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = alloc_ids(c, ids0);
+    if (e != hipSuccess)
+      return undo(fail(e == hipErrorOutOfMemory ? RK_E_NOMEM : RK_E_DEVICE, hipGetErrorString(e)));
+    rk_status st = ensure_batch_ws(h, c->ws, chunk, c->stream);
+    if (st != RK_OK) return undo(st);
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   const int32_t ci = (int32_t)s->cats.size();
   *catalog = ci;
-  s->cats.push_back(c);
-  c->worker = std::thread([s, ci, c] { s->loop(ci, c); });
+  s->cats.push_back(cat);
+  for (ServerSlot* c : cat->slots) c->worker = std::thread([s, ci, cat, c] { s->loop(ci, cat, c); });
   return RK_OK;
 }
 
@@ -1253,10 +1402,13 @@ rk_status rk_server_submit(rk_server* s, int32_t catalog, const float* q, int32_
   r.tag = tag;
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    ServerCatalog* cat = s->cats[catalog];
+    if ((int64_t)cat->queue.size() >= s->opts.max_queue)
+      return fail(RK_E_BUSY, "the catalog's queue is full (max_queue)");
     r.t_submit = ms_since(s->t0);
-    s->cats[catalog]->queue.push_back(std::move(r));
+    cat->queue.push_back(std::move(r));
     ++s->inflight;
-    s->cats[catalog]->cv.notify_one();
+    cat->cv.notify_one();
   }
   return RK_OK;
 }
@@ -1286,14 +1438,30 @@ rk_status rk_server_submit_many(rk_server* s, int64_t n, const int32_t* catalog,
   }
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    std::vector<int64_t> add(s->cats.size(), 0);
+    for (int64_t i = 0; i < n; ++i) ++add[catalog[i]];
+    for (size_t c = 0; c < s->cats.size(); ++c)
+      if ((int64_t)s->cats[c]->queue.size() + add[c] > s->opts.max_queue)
+        return fail(RK_E_BUSY, "catalog " + std::to_string(c) + ": the queue has no room for " +
+                                   std::to_string(add[c]) + " more requests (max_queue)");
     const double now = ms_since(s->t0);
     for (int64_t i = 0; i < n; ++i) {
       rs[i].t_submit = arrival_ms ? std::min(arrival_ms[i], now) : now;
       s->cats[catalog[i]]->queue.push_back(std::move(rs[i]));
     }
     s->inflight += n;
-    for (int64_t i = 0; i < n; ++i) s->cats[catalog[i]]->cv.notify_one();
+    for (size_t c = 0; c < s->cats.size(); ++c)
+      if (add[c]) s->cats[c]->cv.notify_all();
   }
+  return RK_OK;
+}
+
+rk_status rk_server_catalog_state(rk_server* s, int32_t catalog, int64_t* queued, int32_t* running) {
+  if (!s || !queued || !running) return fail(RK_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (catalog < 0 || catalog >= (int32_t)s->cats.size()) return fail(RK_E_INVAL, "no such catalog");
+  *queued = (int64_t)s->cats[catalog]->queue.size();
+  *running = s->cats[catalog]->running;
   return RK_OK;
 }
 

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librkmips.so")
 
-RK_OK, RK_E_INVAL, RK_E_KMAX, RK_E_NOMEM, RK_E_TRUNC, RK_E_DEVICE = range(6)
+RK_OK, RK_E_INVAL, RK_E_KMAX, RK_E_NOMEM, RK_E_TRUNC, RK_E_DEVICE, RK_E_BUSY = range(7)
 RK_FP32, RK_BF16 = 0, 1
 (RK_F_PERM_Q, RK_F_PERM_P, RK_F_SQNORM_Q, RK_F_SQNORM_P, RK_F_NORM_Q, RK_F_NORM_P,
  RK_F_L64, RK_F_L32, RK_F_LB, RK_F_BNORM) = range(10)
@@ -31,7 +31,7 @@ EXPORTS = [
     "rk_index_free", "rk_last_error",
     "rk_server_opts_default", "rk_server_create", "rk_server_add_catalog", "rk_server_submit",
     "rk_server_poll", "rk_server_inflight", "rk_server_used_bytes", "rk_server_free",
-    "rk_server_submit_many", "rk_server_now_ms",
+    "rk_server_submit_many", "rk_server_now_ms", "rk_server_catalog_state",
 ]
 
 
@@ -71,8 +71,9 @@ class Stats(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("max_wait_us", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_int64), ("reserved", ctypes.c_int64 * 6)]
+                ("max_wait_us", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64), ("max_queue", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 5)]
 
 
 class Completion(ctypes.Structure):
@@ -159,6 +160,8 @@ def lib():
     L.rk_server_submit_many.restype = ctypes.c_int
     L.rk_server_now_ms.argtypes = [vp]
     L.rk_server_now_ms.restype = f64
+    L.rk_server_catalog_state.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.rk_server_catalog_state.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -331,17 +334,20 @@ class Index:
 
 
 class Server:
-    """Continuous-batching server over resident catalogs (rk_server_*).
+    """Continuous-batching server over resident catalogs (rk_server_*): per
+    catalog, `slots` launches in flight, each taking the queued requests when
+    it is free.
 
     The indices added as catalogs are borrowed: keep them alive and do not
     query them directly while the server runs (this object holds references).
     """
 
     def __init__(self, max_batch: int = 1024, max_wait_us: int = 0, hbm_budget: int = 0,
-                 device: int = 0):
+                 device: int = 0, slots: int = 0, max_queue: int = 0):
         o = ServerOpts()
         lib().rk_server_opts_default(ctypes.byref(o))
         o.device, o.max_batch, o.max_wait_us, o.hbm_budget = device, max_batch, max_wait_us, hbm_budget
+        o.slots, o.max_queue = slots, max_queue
         h = ctypes.c_void_p()
         _check(lib().rk_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -397,6 +403,12 @@ class Server:
 
     def inflight(self) -> int:
         return lib().rk_server_inflight(self._h)
+
+    def catalog_state(self, catalog: int) -> tuple[int, int]:
+        """(queued requests, slots with a launch in flight) of a catalog."""
+        q, r = ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().rk_server_catalog_state(self._h, int(catalog), ctypes.byref(q), ctypes.byref(r)))
+        return q.value, r.value
 
     def used_bytes(self) -> int:
         return lib().rk_server_used_bytes(self._h)

@@ -1,13 +1,14 @@
 """GPU tests of the serving runtime (rk_server_*): continuous batching over
-several resident catalogs, admission by device-memory footprint, and result
-sets equal to the float64 oracle per request, through the C ABI."""
+several resident catalogs (several launches in flight per catalog), admission
+by device-memory footprint and a bounded queue, and result sets equal to the
+float64 oracle per request, through the C ABI."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2110_07131_amd import datagen
-from paper_2110_07131_amd.rkmips import (RK_E_INVAL, RK_E_KMAX, RK_E_NOMEM, Index, RkError,
-                                         Server)
+from paper_2110_07131_amd.rkmips import (RK_E_BUSY, RK_E_INVAL, RK_E_KMAX, RK_E_NOMEM, Index,
+                                         RkError, Server)
 
 pytestmark = pytest.mark.gpu
 
@@ -147,5 +148,133 @@ def test_large_results_grow_buffers():
     sizes = [len(got[t][1]) for t in range(40)]
     assert max(sizes) > 65536
     check([(w, 15, idx)], [0], reqs, got)
+    srv.close()
+    idx.free()
+
+
+def sampled_oracle(Q, P, kmax, n_sample, seed):
+    """Oracle on a user sample holding the first and last norm-sorted blocks."""
+    n = Q.shape[0]
+    perm = oracle.sort_desc(oracle.sqnorms(Q))
+    edge = np.concatenate([perm[:64], perm[(n - 1) // 64 * 64:]])
+    rng = np.random.default_rng(seed)
+    us = np.union1d(edge, rng.choice(n, n_sample, replace=False)).astype(np.int32)
+    Qs = np.ascontiguousarray(Q[us])
+    th = oracle.theta(Qs, P, kmax)
+
+    def want(q, k):
+        return us[oracle.theta_query(th, Qs, q, int(k))]
+
+    def restrict(ids):
+        return ids[np.isin(ids, us, assume_unique=True)]
+    return want, restrict
+
+
+def wait_done(srv, tags, timeout_s=120.0):
+    import time
+    got, t_end = {}, time.time() + timeout_s
+    while len(got) < len(tags):
+        assert time.time() < t_end, "requests did not finish"
+        for tag, cat, status, ids, t0, t1 in srv.poll(wait_us=20000):
+            assert status == 0, (tag, status)
+            got[tag] = (ids, t0, t1)
+    return got
+
+
+def test_late_request_overlaps_a_long_batch_of_the_same_catalog():
+    # 400,000 users x 100,000 items, d = 100, the paper's index (P' = 2 k_max):
+    # a launch of 4,096 queries runs for tens of milliseconds (four query
+    # chunks of linear scans).  A request submitted while it is on the
+    # device is taken by the catalog's second slot and finishes first; its
+    # result equals the oracle's and the result of the same request alone.
+    import time
+    w = datagen.workload(400_000, 100_000, 100, 0.5, 4097, seed=70, k_choices="uniform", k_max=25)
+    idx = Index.build(w.Q, w.P, 25, lb_items=50)
+    srv = Server(max_batch=4096, slots=2)
+    cat = srv.add(idx)
+    q1, k1 = np.ascontiguousarray(w.queries[-1]), 10
+    srv.submit(cat, q1, k1, 0)                       # alone
+    alone = wait_done(srv, [0])[0]
+    long_qs, long_ks = w.queries[:4096], w.ks[:4096]
+    srv.submit_many([cat] * 4096, list(long_qs), long_ks, np.arange(100, 4196))
+    t_end = time.time() + 30
+    while srv.catalog_state(cat) != (0, 1):          # the long batch is on the device
+        assert time.time() < t_end
+        time.sleep(0.0005)
+    srv.submit(cat, q1, k1, 1)                       # late, same catalog
+    got = wait_done(srv, [1] + list(range(100, 4196)))
+    srv.close()
+    ids1, sub1, done1 = got[1]
+    long_done = max(got[t][2] for t in range(100, 4196))
+    long_sub = min(got[t][1] for t in range(100, 4196))
+    assert sub1 > long_sub and done1 < long_done, (sub1, done1, long_sub, long_done)
+    assert np.array_equal(ids1, alone[0])
+    want, restrict = sampled_oracle(w.Q, w.P, 25, 2000, seed=71)
+    assert np.array_equal(restrict(ids1), want(q1, k1))
+    for t in range(100, 4196, 41):
+        assert np.array_equal(restrict(got[t][0]), want(long_qs[t - 100], long_ks[t - 100])), t
+    idx.free()
+
+
+def test_bounded_queue_rejects_when_full():
+    cats = catalogs()
+    srv = Server(max_batch=8, max_queue=5)
+    srv.add(cats[0][2])
+    w = cats[0][0]
+    qs = [np.ascontiguousarray(w.P[i]) for i in range(6)]
+    with pytest.raises(RkError) as e:            # six at once never fit a queue of five
+        srv.submit_many([0] * 6, qs, [3] * 6, list(range(6)))
+    assert e.value.status == RK_E_BUSY
+    assert srv.inflight() == 0
+    srv.submit_many([0] * 5, qs[:5], [3] * 5, list(range(5)))
+    got = wait_done(srv, list(range(5)))
+    for t in range(5):
+        assert np.array_equal(got[t][0], oracle.brute(w.Q, w.P, qs[t], 3))
+    srv.close()
+
+
+def large_result_case():
+    w = datagen.workload(120_000, 20, 8, 0.3, 20, seed=9)
+    idx = Index.build(w.Q, w.P, 15)
+    reqs = [(t, 0, np.ascontiguousarray(w.P[t % 20]), 12 + t % 4) for t in range(32)]
+    return w, idx, reqs
+
+
+def test_result_growth_within_budget_splits_batches():
+    # the budget leaves room for one request's ids but not a whole batch's:
+    # batches run in halves until their ids fit
+    w, idx, reqs = large_result_case()
+    probe = Server(max_batch=16, slots=1)
+    probe.add(idx)
+    need = probe.used_bytes()
+    probe.close()
+    biggest = max(oracle.brute(w.Q, w.P, q, k).size for _, _, q, k in reqs[:4])
+    srv = Server(max_batch=16, slots=1, hbm_budget=need + 4 * (2 * biggest + 4096))
+    srv.add(idx)
+    got = serve(srv, [0], reqs)
+    check([(w, 15, idx)], [0], reqs, got)
+    assert srv.used_bytes() <= need + 4 * (2 * biggest + 4096)
+    srv.close()
+    idx.free()
+
+
+def test_result_beyond_budget_fails_that_request():
+    w, idx, reqs = large_result_case()
+    probe = Server(max_batch=16, slots=1)
+    probe.add(idx)
+    need = probe.used_bytes()
+    probe.close()
+    srv = Server(max_batch=16, slots=1, hbm_budget=need)
+    srv.add(idx)
+    srv.submit(0, reqs[0][2], reqs[0][3], 0)
+    small_q = np.ascontiguousarray(1e-3 * w.P[0])  # k = 1: almost no members, fits the first buffer
+    srv.submit(0, small_q, 1, 1)
+    out = {}
+    while len(out) < 2:
+        for tag, cat, status, ids, t0, t1 in srv.poll(wait_us=20000):
+            out[tag] = (status, ids)
+    assert out[0][0] == RK_E_NOMEM
+    assert out[1][0] == 0 and np.array_equal(out[1][1], oracle.brute(w.Q, w.P, small_q, 1))
+    assert srv.used_bytes() == need
     srv.close()
     idx.free()
