@@ -190,6 +190,27 @@ rk_status rk_reverse_kmips_batch_dev(rk_index *idx, const float *qs_dev,
                                      int64_t *offsets_dev, int32_t *ids_dev,
                                      int64_t cap, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the batch
+ * of rk_reverse_kmips_batch_dev, same arguments and results, with no
+ * allocation of any kind.  Its workspace (result bitmaps, query tiles,
+ * pair slots) is one static 64 MiB device array per GPU, held until the
+ * process ends and shared by every call of this function on that GPU: calls
+ * that overlap on one GPU (other streams or threads) race and must not be
+ * made.  The array keeps the last call's contents; each call clears what
+ * must start at zero.  Chunks of queries are sized to fit the array (at
+ * least 64 queries per chunk: RK_E_INVAL for an index whose 64-query chunk
+ * needs more, i.e. beyond about 7.5 million users).  Exact lower-bound
+ * tables only (lb_items 0 or m; RK_E_INVAL otherwise, and for tiles too
+ * wide for the batched kernels).  k > k_max (and k <= m) is RK_E_KMAX even
+ * with auto_rebuild, since a rebuild allocates.  ks_host is copied to the
+ * device with a stream-ordered copy from the caller's memory: keep it
+ * unchanged until the stream has passed this call. */
+rk_status rk_reverse_kmips_batch_dev_noalloc(rk_index *idx, const float *qs_dev,
+                                             int64_t nq, const int32_t *ks_host,
+                                             int64_t *offsets_dev, int32_t *ids_dev,
+                                             int64_t cap, void *stream);
+
 /* One query with per-user decision classes (rk_class, one byte per user,
  * indexed by original id; users never evaluated keep RK_C_BLOCK_NO) and
  * optionally the bulk-precision u.q (float per original id; NaN where not

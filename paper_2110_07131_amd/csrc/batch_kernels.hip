@@ -1666,6 +1666,12 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
     p[i] = v;
 }
 
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+}
+
 void launch_bscan_reset(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
   if (ix.exact || ix.n_pad == 0) return;
   const int64_t blocks = std::min<int64_t>((ix.n_pad + 255) / 256, 4096);

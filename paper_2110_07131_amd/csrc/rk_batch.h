@@ -80,6 +80,8 @@ void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 size_t bscan_lds_bytes(const DevIndex& ix);
 // whether the scan's workgroup (dynamic and static LDS) fits a CU
 bool bscan_fits(const DevIndex& ix);
+// p[0..n) = v (a fill kernel: stream-ordered, and capturable in a graph).
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 // Bounded table: the carried scan state starts empty for a batch call.
 void launch_bscan_reset(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 // offs[0] must hold the chunk's first offset; writes offs[1..nq] and ids.

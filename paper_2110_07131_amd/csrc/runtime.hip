@@ -13,6 +13,7 @@
 #include <numeric>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "rk_batch.h"
@@ -677,10 +678,14 @@ bool batch_one_at_a_time(const DevIndex& ix) {
 }
 
 // Enqueues a batch on stream s with workspace b (per-kernel event timing
-// only when `timed`, for the index's own calls).
+// only when `timed`, for the index's own calls).  chunk > 0: queries per
+// chunk, for a workspace already laid out for it (no growth); direct_ks: the
+// k values go to the device straight from the caller's memory instead of
+// through the workspace's pinned staging.
 rk_status batch_enqueue(rk_index* h, BatchWS& b, const float* qs_dev, int64_t nq,
                         const int32_t* ks, int64_t* offs, int32_t* ids, int64_t cap,
-                        hipStream_t s, bool timed) {
+                        hipStream_t s, bool timed, int32_t chunk_fixed = 0,
+                        bool direct_ks = false) {
   const DevIndex& ix = h->ix;
   launch_set_i64(offs, 0, s);
   HIPTRY(hipGetLastError());
@@ -695,12 +700,16 @@ rk_status batch_enqueue(rk_index* h, BatchWS& b, const float* qs_dev, int64_t nq
     return RK_OK;
   }
   const int64_t W = bitmap_words(ix.n);
-  const int32_t chunk = batch_chunk(h, nq);
-  rk_status st = ensure_batch_ws(h, b, chunk, s);
-  if (st != RK_OK) return st;
+  const int32_t chunk = chunk_fixed > 0 ? chunk_fixed : batch_chunk(h, nq);
+  rk_status st = RK_OK;
+  if (chunk_fixed <= 0 && (st = ensure_batch_ws(h, b, chunk, s)) != RK_OK) return st;
   for (int64_t c0 = 0; c0 < nq; c0 += chunk) {
     const int32_t nc = (int32_t)std::min<int64_t>(chunk, nq - c0);
-    if ((st = stage_ks(b, ks + c0, nc, b.ks_dev, s)) != RK_OK) return st;
+    if (direct_ks) {
+      HIPTRY(hipMemcpyAsync(b.ks_dev, ks + c0, nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    } else if ((st = stage_ks(b, ks + c0, nc, b.ks_dev, s)) != RK_OK) {
+      return st;
+    }
     BatchView bv{};
     bv.qs = qs_dev + c0 * ix.d;
     bv.qn = b.qn; bv.perm = b.perm; bv.qt = b.qt; bv.qb = b.qb;
@@ -726,6 +735,74 @@ rk_status batch_enqueue(rk_index* h, BatchWS& b, const float* qs_dev, int64_t nq
     h->queries += nc;
   }
   return RK_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Workspace for callers that cannot allocate
+// (rk_reverse_kmips_batch_dev_noalloc): one static device array per GPU,
+// shared by every such call on that GPU and kept until the process ends.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device (in host code `scratch` names a host-side stand-in, not this address).
+rk_status scratch_for(int device, unsigned char** out) {
+  if (device < 0 || device >= kScratchDevices) return fail(RK_E_INVAL, "device ordinal too large");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(RK_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = (unsigned char*)p;
+  }
+  *out = g_scratch_ptr[device];
+  return RK_OK;
+}
+
+// Lays out the exact-table batch workspace for chunks of `chunk` queries in
+// [base, base + bytes), pair slots last with whatever is left (at most the
+// regular budget; pairs beyond them are decided in float64 by the filter).
+// Returns the bytes the layout needs without pair slots (> bytes: no fit).
+size_t carve_ws(const rk_index* h, BatchWS& b, int32_t chunk, unsigned char* base, size_t bytes) {
+  const DevIndex& ix = h->ix;
+  const int64_t cp = round_up(chunk, TILE), W = bitmap_words(ix.n);
+  size_t off = 0;
+  auto take = [&](auto** p, int64_t count) {
+    off = (size_t)round_up((int64_t)off, 256);
+    *p = reinterpret_cast<std::remove_reference_t<decltype(**p)>*>(base + off);
+    off += (size_t)std::max<int64_t>(count, 1) * sizeof(**p);
+  };
+  b = BatchWS();
+  take(&b.bits, (int64_t)chunk * std::max<int64_t>(W, 1));
+  take(&b.counts, chunk);
+  take(&b.qn, chunk);
+  take(&b.perm, chunk);
+  take(&b.qt, cp * (ix.d + (ix.d & 1)));
+  if (ix.bf16) take(&b.qb, cp * ix.d16);
+  take(&b.qn_s, cp);
+  take(&b.k_s, cp);
+  take(&b.kofs_s, cp);
+  take(&b.all, chunk);
+  take(&b.npairs, 1);
+  take(&b.ks_dev, chunk);
+  const size_t fixed = off;
+  const size_t left = bytes > fixed + 4 * 256 ? bytes - fixed - 4 * 256 : 0;
+  const int64_t pc = std::min<int64_t>(batch_sizes(h, chunk).pc, (int64_t)(left / 12));
+  take(&b.pair_u, pc);
+  take(&b.pair_j, pc);
+  take(&b.pair_s, pc);
+  b.pair_cap = pc;
+  b.qcap = chunk;
+  return fixed;
 }
 
 }  // namespace
@@ -1131,6 +1208,52 @@ rk_status rk_reverse_kmips_batch_dev(rk_index* h, const float* qs_dev, int64_t n
   HIPTRY(hipSetDevice(h->device));
   hipStream_t s = stream ? (hipStream_t)stream : h->stream;
   return batch_enqueue(h, h->bw, qs_dev, nq, ks, offsets_dev, ids_dev, cap, s, true);
+}
+
+rk_status rk_reverse_kmips_batch_dev_noalloc(rk_index* h, const float* qs_dev, int64_t nq,
+                                             const int32_t* ks, int64_t* offsets_dev,
+                                             int32_t* ids_dev, int64_t cap, void* stream) {
+  if (!h || nq < 0 || (nq > 0 && (!qs_dev || !ks)) || !offsets_dev || cap < 0 || (cap > 0 && !ids_dev))
+    return fail(RK_E_INVAL, "NULL argument or negative size");
+  if (nq > INT32_MAX) return fail(RK_E_INVAL, "nq too large");
+  const DevIndex& ix = h->ix;
+  if (!ix.exact) return fail(RK_E_INVAL, "noalloc batch: needs an exact lower-bound table (lb_items 0 or m)");
+  if (batch_one_at_a_time(ix)) return fail(RK_E_INVAL, "noalloc batch: tiles too wide for the batched kernels");
+  for (int64_t i = 0; i < nq; ++i) {
+    if (ks[i] < 1) return fail(RK_E_INVAL, "k must be >= 1");
+    if (ks[i] > ix.kmax && ks[i] <= ix.m)
+      return fail(RK_E_KMAX, "noalloc batch: k > k_max (a rebuild would allocate)");
+  }
+  HIPTRY(hipSetDevice(h->device));
+  hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+  unsigned char* base = nullptr;
+  rk_status st = scratch_for(h->device, &base);
+  if (st != RK_OK) return st;
+  if (nq == 0 || ix.n == 0) {  // every row is empty
+    launch_fill_i32((int32_t*)offsets_dev, 2 * (nq + 1), 0, s);
+    HIPTRY(hipGetLastError());
+    return RK_OK;
+  }
+  // the largest chunk (a power-of-two fraction of the regular one, at least
+  // 64 queries) whose workspace fits with room for 64 Ki pair slots
+  int32_t chunk = batch_chunk(h, nq);
+  BatchWS b;
+  for (;;) {
+    const size_t fixed = carve_ws(h, b, chunk, base, kScratchBytes);
+    const int64_t want_pairs = std::min<int64_t>(batch_sizes(h, chunk).pc, 1 << 16);
+    if (fixed + 4 * 256 + (size_t)want_pairs * 12 <= kScratchBytes) break;
+    if (chunk <= TILE)
+      return fail(RK_E_INVAL, "noalloc batch: " + std::to_string(ix.n) + " users need more than the " +
+                                  std::to_string(kScratchBytes >> 20) + " MiB static workspace");
+    chunk = std::max<int32_t>(TILE, chunk / 2);
+  }
+  // the array keeps the last call's contents: result bits and counts must
+  // start at zero (the assembly clears them again after each chunk)
+  const int64_t W = bitmap_words(ix.n);
+  launch_fill_i32((int32_t*)b.bits, (int64_t)chunk * std::max<int64_t>(W, 1), 0, s);
+  launch_fill_i32((int32_t*)b.counts, 2 * (int64_t)chunk, 0, s);
+  HIPTRY(hipGetLastError());
+  return batch_enqueue(h, b, qs_dev, nq, ks, offsets_dev, ids_dev, cap, s, false, chunk, true);
 }
 
 rk_status rk_reverse_kmips_batch(rk_index* h, const float* qs, int64_t nq, const int32_t* ks,

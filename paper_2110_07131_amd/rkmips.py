@@ -26,6 +26,7 @@ EXPORTS = [
     "rk_build_opts_default", "rk_build_index", "rk_build_index_dev", "rk_reverse_kmips",
     "rk_reverse_kmips_dev", "rk_reverse_kmips_batch", "rk_reverse_kmips_batch_dev",
     "rk_reverse_kmips_trace", "rk_index_set_timing", "rk_index_kernel_times",
+    "rk_reverse_kmips_batch_dev_noalloc",
     "rk_index_set_counting", "rk_index_stats",
     "rk_index_reset_counters", "rk_index_export", "rk_index_rebuild", "rk_index_footprint",
     "rk_index_free", "rk_last_error",
@@ -118,6 +119,8 @@ def lib():
     L.rk_reverse_kmips_batch.restype = ctypes.c_int
     L.rk_reverse_kmips_batch_dev.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
     L.rk_reverse_kmips_batch_dev.restype = ctypes.c_int
+    L.rk_reverse_kmips_batch_dev_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
+    L.rk_reverse_kmips_batch_dev_noalloc.restype = ctypes.c_int
     L.rk_reverse_kmips_trace.argtypes = [vp, vp, i32, vp, vp]
     L.rk_reverse_kmips_trace.restype = ctypes.c_int
     L.rk_index_set_timing.argtypes = [vp, i32]
@@ -283,6 +286,16 @@ class Index:
     def reverse_kmips_batch_dev(self, qs_dev, ks_host, offsets_dev, ids_dev, stream=None):
         ks = np.ascontiguousarray(ks_host, np.int32)
         _check(lib().rk_reverse_kmips_batch_dev(
+            self._h, ctypes.c_void_p(qs_dev.data_ptr()), qs_dev.shape[0], _ptr(ks),
+            ctypes.c_void_p(offsets_dev.data_ptr()), ctypes.c_void_p(ids_dev.data_ptr()),
+            ids_dev.numel(), ctypes.c_void_p(stream) if stream else None))
+
+    def reverse_kmips_batch_dev_noalloc(self, qs_dev, ks_host, offsets_dev, ids_dev, stream=None):
+        """As reverse_kmips_batch_dev, with the library's static workspace
+        (no allocation); keep ks_host alive until the stream passes the call."""
+        ks = np.ascontiguousarray(ks_host, np.int32)
+        self._noalloc_ks = ks
+        _check(lib().rk_reverse_kmips_batch_dev_noalloc(
             self._h, ctypes.c_void_p(qs_dev.data_ptr()), qs_dev.shape[0], _ptr(ks),
             ctypes.c_void_p(offsets_dev.data_ptr()), ctypes.c_void_p(ids_dev.data_ptr()),
             ids_dev.numel(), ctypes.c_void_p(stream) if stream else None))
