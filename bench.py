@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--form-steps", type=int, default=5)
     ap.add_argument("--handoff-tiles", type=int, default=0,
                     help="index option handoff_tiles (bounded table; 0 = the library default)")
+    ap.add_argument("--block-size", type=int, default=0,
+                    help="users per Lemma 3 block (16, 32 or 64; 0 = 64)")
+    ap.add_argument("--no-blocks", action="store_true",
+                    help="no Lemma 3 filter (the paper's Simpfer without blocks)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -360,7 +364,8 @@ def main():
 
     t0 = time.perf_counter()
     idx = Index.build(w.Q, w.P, kmax, precision=args.precision, lb_items=args.lb_items,
-                      handoff_tiles=args.handoff_tiles)
+                      handoff_tiles=args.handoff_tiles, block_size=args.block_size,
+                      no_blocks=args.no_blocks)
     build_s = time.perf_counter() - t0
     st0 = idx.stats()
     print(f"[bench] index built in {build_s:.2f} s", file=sys.stderr, flush=True)
@@ -497,6 +502,7 @@ def main():
                                f"{args.precision} bulk products, "
                                f"{'exact' if args.lb_items in (0, m) else 'P=' + str(args.lb_items)} lower-bound table",
                    "queries_per_step": nq, "lb_items": args.lb_items or m,
+                   "block_size": args.block_size or 64, "lemma3_blocks": not args.no_blocks,
                    "precision": args.precision, "form": "device-resident batch, CSR output"},
         "p50_ms": batch_lat["p50_ms"], "p99_ms": batch_lat["p99_ms"],
         "latency": batch_lat, "single_query_latency": lat,

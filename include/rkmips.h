@@ -64,8 +64,12 @@ typedef struct {
                              and every decision is a single certified compare.
                              k_max..m = the paper's P' prefix (its experiments
                              use O(k_max)); values above m are clamped to m. */
-    int32_t block_size;   /* users per block (Definition 5); 0 or 64 only:
-                             one block is one 64-lane wavefront */
+    int32_t block_size;   /* users per block of the Lemma 3 filter
+                             (Definition 5, Equation (1)): 0 -> 64 (one block
+                             = one 64-lane wavefront), 16 or 32 (the kernels
+                             still work in 64-user tiles; a tile is skipped
+                             when all its blocks are pruned, and the pairs of
+                             pruned blocks inside a live tile are not tested) */
     int32_t device;       /* HIP device ordinal */
     double margin_rel;    /* extra relative margin: the certified tests use
                              max(margin_rel, rigorous bound) * |u||q| */
@@ -85,7 +89,10 @@ typedef struct {
                              scanning are handed to a group pass of users from
                              several blocks only with more than this many
                              64-item tiles left (a tuning and test hook) */
-    int32_t reserved[4];
+    int32_t no_blocks;    /* nonzero: no Lemma 3 filter (every block is
+                             evaluated: the paper's "Simpfer without blocks",
+                             Section 5.2); results are unchanged */
+    int32_t reserved[3];
 } rk_build_opts;
 
 /* Counters and sizes of an index.  Query counters accumulate over every
@@ -99,7 +106,8 @@ typedef struct {
     int64_t build_cand_overflow_users;
     int64_t rebuilds;
     int64_t queries;
-    int64_t blocks_visited;    /* (block, query) pairs tested with Lemma 3 */
+    int64_t blocks_visited;    /* (block, query) pairs tested with Lemma 3
+                                  (block = block_size users) */
     int64_t blocks_pruned;     /* ... and pruned by it */
     int64_t users_evaluated;   /* u.q computed (users of unpruned blocks) */
     int64_t lemma1_no;         /* certified no by Lemma 1 */

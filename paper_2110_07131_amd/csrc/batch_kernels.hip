@@ -291,12 +291,17 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   p += 2 * TILE * 4;
   int32_t* meta_k2 = (int32_t*)p;  // [2][64] their k's rows in the (k, user) tables
   p += 2 * TILE * 4;
-  unsigned long long* masks = (unsigned long long*)p;
-  p += (kBatchChunkMax / TILE) * 8;
+  // Lemma 3 blocks of bsize users: nsb per 64-user tile, a live-query mask
+  // per (block, query tile), and with nsb > 1 their union (the tile walk)
+  constexpr int MT = kBatchChunkMax / TILE;
+  const int nsb = TILE / ix.bsize;
+  unsigned long long* masks = (unsigned long long*)p;  // [nsb][MT] (+ [MT] union)
+  unsigned long long* walk = masks + (nsb > 1 ? nsb * MT : 0);
+  p += (nsb > 1 ? nsb + 1 : 1) * MT * 8;
   float* Ll = (float*)p;
   p += ix.kmax * TILE * 4;
-  float* LBl = (float*)p;
-  p += ix.kmax * 4;
+  float* LBl = (float*)p;  // [nsb][kmax]
+  p += ix.kmax * nsb * 4;
   p += ix.kmax * 4;
   float* Yl = (float*)p;  // [kmax][64] "yes" thresholds per (k, user)
 
@@ -313,7 +318,8 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   }
   for (int i = t; i < ix.kmax * TILE; i += 256)
     Ll[i] = ix.L32[(int64_t)(i / TILE) * ix.n_pad + B * TILE + (i % TILE)];
-  for (int i = t; i < ix.kmax; i += 256) LBl[i] = ix.LB[(int64_t)i * ix.nB + B];
+  for (int i = t; i < ix.kmax * nsb; i += 256)
+    LBl[i] = ix.LB[(int64_t)(i % ix.kmax) * ix.nSB + B * nsb + i / ix.kmax];
   // yes threshold of (k, user): exact table -> the float above L (>= theta_k);
   // bounded table -> Lemma 2's bound cs_inflate |u|^ |p_k|^
   for (int i = t; i < ix.kmax * TILE; i += 256) {
@@ -325,23 +331,34 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   }
   __syncthreads();
 
-  // Lemma 3 for every query of the chunk: query j lives iff
-  // cs_inflate * |u_first| * |q_j| >= L^k(B).
-  const float csb = ix.cs_inflate * ix.bnorm[B];
+  // Lemma 3 for every query of the chunk and every block b of the tile:
+  // query j lives iff cs_inflate * |u_first(b)| * |q_j| >= L^k(b).
   unsigned long long c_vis = 0, c_pr = 0;
-  for (int base = 0; base < bv.nq_pad; base += 256) {
-    const int j = base + t;
-    int kq = 0;
-    float nqq = 0.f;
-    if (j < bv.nq_pad) {
-      kq = bv.k_s[j];
-      nqq = bv.qn_s[j];
+  for (int sb = 0; sb < nsb; ++sb) {
+    const float csb = ix.cs_inflate * ix.bnorm[B * nsb + sb];
+    const float* lbs = LBl + sb * ix.kmax;
+    for (int base = 0; base < bv.nq_pad; base += 256) {
+      const int j = base + t;
+      int kq = 0;
+      float nqq = 0.f;
+      if (j < bv.nq_pad) {
+        kq = bv.k_s[j];
+        nqq = bv.qn_s[j];
+      }
+      const bool live = kq > 0 && !(ix.use_blocks && csb * nqq < lbs[kq > 0 ? kq - 1 : 0]);
+      const unsigned long long m = __ballot(live);
+      if (lane == 0 && base + wave * TILE < bv.nq_pad) masks[sb * MT + (base + wave * TILE) / TILE] = m;
+      c_vis += kq > 0;
+      c_pr += kq > 0 && !live;
     }
-    const bool live = kq > 0 && !(csb * nqq < LBl[kq > 0 ? kq - 1 : 0]);
-    const unsigned long long m = __ballot(live);
-    if (lane == 0 && base + wave * TILE < bv.nq_pad) masks[(base + wave * TILE) / TILE] = m;
-    c_vis += kq > 0;
-    c_pr += kq > 0 && !live;
+  }
+  if (nsb > 1) {
+    __syncthreads();
+    for (int T0 = t; T0 < bv.nq_pad / TILE; T0 += 256) {
+      unsigned long long u = 0ull;
+      for (int sb = 0; sb < nsb; ++sb) u |= masks[sb * MT + T0];
+      walk[T0] = u;
+    }
   }
   __syncthreads();
 
@@ -364,8 +381,8 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   int64_t erun0 = 0;
   int erun = 0, efill = 0;
 
-  int T = next_live(masks, 0, nT), slot = 0;
-  int Tn = next_live(masks, T + 1, nT);
+  int T = next_live(walk, 0, nT), slot = 0;
+  int Tn = next_live(walk, T + 1, nT);
   if constexpr (LDSD) {
     if (T < nT) issue_tile(qsrc, bv, T, tile_bytes, lane, wave, qbuf2[0], meta_n2, meta_k2);
     __builtin_amdgcn_s_waitcnt(0);
@@ -389,7 +406,7 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
     const unsigned char* qbuf = qbuf2[slot];
     const float* meta_n = meta_n2 + slot * TILE;
     const int32_t* meta_k = meta_k2 + slot * TILE;
-    const unsigned long long mask = masks[T];
+    const unsigned long long mask = walk[T];
     // this wave's query half may have no live query at all
     const uint32_t hmask = (uint32_t)(mask >> (qhalf * 32));
     if (hmask != 0u) {
@@ -434,7 +451,9 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
     // user) in LDS.  e = eps|u||q| + eps_abs; both tests round relative to
     // |u||q|, which the slack inside eps covers.
     // the lane's rows are qhalf*32 + g*8 + half*4 + i  (r = 4g + i)
-    const uint32_t hm = hmask >> (half * 4);
+    // the rows live for this lane's own block (blocks of fewer than 64 users)
+    const uint32_t hm = (nsb > 1 ? (uint32_t)(masks[((uh * 32 + col) / ix.bsize) * MT + T] >> (qhalf * 32))
+                                 : hmask) >> (half * 4);
     const uint32_t cells = (hm & 0xFu) | ((hm >> 4) & 0xF0u) | ((hm >> 8) & 0xF00u) |
                            ((hm >> 12) & 0xF000u);
     const int ucol = uh * 32 + col;
@@ -614,13 +633,13 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       T = Tn;
-      Tn = next_live(masks, T + 1, nT);
+      Tn = next_live(walk, T + 1, nT);
       slot ^= 1;
     } else {
       __syncthreads();
       if (Tn < nT) commit_tile(qbuf2[0], meta_n2, meta_k2, tile_vecs, t, pf, pf_n, pf_k);
       T = Tn;
-      Tn = next_live(masks, T + 1, nT);
+      Tn = next_live(walk, T + 1, nT);
       __syncthreads();
       if (Tn < nT) stage_tile((const u32x4*)qsrc, bv, Tn, tile_vecs, t, pf, pf_n, pf_k);
     }
@@ -1712,8 +1731,10 @@ void launch_bprep(const DevIndex& ix, const BatchView& bv, const int32_t* ks_dev
 size_t bfilter_lds_bytes(const DevIndex& ix) {
   const size_t tile = ix.bf16 ? (size_t)(ix.d16 / 8) * TILE * 16 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
   const bool ldsd = ix.bf16 && (tile / 16 + 255) / 256 <= 2;  // the kernel's direct-load case (NV <= 2)
-  return (ldsd ? 3 : 2) * ((tile + 15) / 16 * 16) + 4 * TILE * 4 + (kBatchChunkMax / TILE) * 8 +
-         2 * (size_t)ix.kmax * TILE * 4 + (size_t)ix.kmax * 8;
+  const size_t nsb = TILE / ix.bsize;
+  return (ldsd ? 3 : 2) * ((tile + 15) / 16 * 16) + 4 * TILE * 4 +
+         (nsb > 1 ? nsb + 1 : 1) * (kBatchChunkMax / TILE) * 8 + 2 * (size_t)ix.kmax * TILE * 4 +
+         (size_t)ix.kmax * 4 * (nsb + 1);
 }
 
 // Largest query tile the filter's prefetch registers hold.

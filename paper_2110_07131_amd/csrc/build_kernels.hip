@@ -389,22 +389,23 @@ void launch_lb_overflow(const DevIndex& ix, int64_t S_end, const int32_t* ovf_li
 }
 
 // ---------------------------------------------------------------------------
-// Blocks (Definition 5, Equation (1)): LB[j][B] = min of L32[j][.] over the
-// real users of block B; bnorm[B] = norm of its first (largest-norm) user.
+// Blocks (Definition 5, Equation (1)) of bsize users: LB[j][b] = min of
+// L32[j][.] over the real users of block b (+inf when it has none);
+// bnorm[b] = norm of its first (largest-norm) user.
 __global__ void k_blocks(DevIndex ix, float* __restrict__ LB, float* __restrict__ bnorm) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)ix.kmax * ix.nB;
+  const int64_t total = (int64_t)ix.kmax * ix.nSB;
   if (t >= total) return;
-  const int64_t j = t / ix.nB, B = t % ix.nB;
+  const int64_t j = t / ix.nSB, b = t % ix.nSB;
   float lo = INFINITY;
-  for (int64_t r = B * TILE; r < (B + 1) * TILE && r < ix.n; ++r)
+  for (int64_t r = b * ix.bsize; r < (b + 1) * ix.bsize && r < ix.n; ++r)
     lo = fminf(lo, ix.L32[j * ix.n_pad + r]);
-  LB[j * ix.nB + B] = lo;
-  if (j == 0) bnorm[B] = ix.normQ[B * TILE];
+  LB[j * ix.nSB + b] = lo;
+  if (j == 0) bnorm[b] = ix.normQ[b * ix.bsize];
 }
 
 void launch_blocks(const DevIndex& ix, float* LB, float* bnorm, hipStream_t s) {
-  const int64_t total = (int64_t)ix.kmax * ix.nB;
+  const int64_t total = (int64_t)ix.kmax * ix.nSB;
   if (total == 0) return;
   hipLaunchKernelGGL(k_blocks, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ix, LB,
                      bnorm);

@@ -111,18 +111,21 @@ __global__ void __launch_bounds__(256) k_filter(DevIndex ix, const float* __rest
   const float nq = wave_qnorm_up(q, ix.d);
   if (B == 0 && lane == 0) *ws.qnorm = nq;
 
-  // Lemma 3: every u of the block has f(q,u) <= cs_inflate*|u_first||q|;
-  // prune when that is strictly below the block's k-th lower bound.
-  const float lbk = ix.LB[(int64_t)(k - 1) * ix.nB + B];
-  const bool pruned = (ix.cs_inflate * ix.bnorm[B]) * nq < lbk;
+  // Lemma 3: every u of a block has f(q,u) <= cs_inflate*|u_first||q|;
+  // prune when that is strictly below the block's k-th lower bound.  The
+  // wave's 64 users hold 64 / bsize blocks; it returns when all are pruned.
+  const int64_t sb = B * (TILE / ix.bsize) + lane / ix.bsize;
+  const float lbk = ix.LB[(int64_t)(k - 1) * ix.nSB + sb];
+  const bool pruned = ix.use_blocks && (ix.cs_inflate * ix.bnorm[sb]) * nq < lbk;
+  const unsigned long long pm = __ballot(pruned);
   if (lane == 0) {
-    ctr_add(ws, C_BLOCKS, 1);
-    if (pruned) ctr_add(ws, C_PRUNED, 1);
+    ctr_add(ws, C_BLOCKS, TILE / ix.bsize);
+    ctr_add(ws, C_PRUNED, __popcll(pm) / ix.bsize);
   }
-  if (pruned) return;
+  if (pm == ~0ull) return;
 
   const int64_t r = B * TILE + lane;
-  const bool valid = r < ix.n;
+  const bool valid = r < ix.n && !pruned;
   const float s = block_dot<BF16>(ix, B, q);
   const float nu = ix.normQ[r];
   const float e = margin(ix, nu, nq);

@@ -58,7 +58,9 @@ struct DevIndex {
   int64_t n, m;          // users, items
   int64_t n_pad, m_pad;  // rounded up to TILE
   int32_t d, d16;        // dimension; bf16 padded dimension (multiple of 16)
-  int32_t kmax, nB, mB;  // k_max; user blocks; item tiles
+  int32_t kmax, nB, mB;  // k_max; user tiles of 64; item tiles
+  int32_t bsize, nSB;    // users per Lemma 3 block (16, 32 or 64); such blocks (n_pad / bsize)
+  int32_t use_blocks;    // 0: Lemma 3 is not applied (every block evaluated)
   int32_t lb_items;      // |P'|
   int32_t exact;         // 1 if L holds the exact k_max largest values over P
   int32_t bf16;          // 1 if the bulk products use the bf16 copies
@@ -73,8 +75,8 @@ struct DevIndex {
   const float* normP;    // [m_pad] norm rounded up (0 for padding)
   const float* L32;      // [kmax][n_pad] lower bounds rounded down
   const double* L64;     // [kmax][n_pad] lower bounds, exact
-  const float* LB;       // [kmax][nB] block minima of L32
-  const float* bnorm;    // [nB] norm of the first user of each block
+  const float* LB;       // [kmax][nSB] block minima of L32
+  const float* bnorm;    // [nSB] norm of the first user of each block
   // Certified-comparison constants (see margin()):
   float eps_rel;         // relative bound on |approx u.x - f(x,u)| / (|u||x|)
   float eps_abs;         // absolute slack (underflow)

@@ -202,7 +202,8 @@ namespace {
 rk_status check_opts(const rk_build_opts& o) {
   if (o.precision != RK_FP32 && o.precision != RK_BF16) return fail(RK_E_INVAL, "precision must be RK_FP32 or RK_BF16");
   if (o.lb_items < 0) return fail(RK_E_INVAL, "lb_items must be >= 0");
-  if (o.block_size != 0 && o.block_size != TILE) return fail(RK_E_INVAL, "block_size must be 0 or 64");
+  if (o.block_size != 0 && o.block_size != 16 && o.block_size != 32 && o.block_size != TILE)
+    return fail(RK_E_INVAL, "block_size must be 0, 16, 32 or 64");
   if (!(o.margin_rel >= 0.0) || !std::isfinite(o.margin_rel) || o.margin_rel >= 0.5)
     return fail(RK_E_INVAL, "margin_rel must be finite, >= 0 and < 0.5");
   if (o.cand_cap < 0) return fail(RK_E_INVAL, "cand_cap must be >= 0");
@@ -234,8 +235,8 @@ rk_status build_bounds(rk_index* h) {
   const int64_t lb = ix.lb_items;
   HIPTRY(h->dalloc(&h->L64, (size_t)ix.kmax * ix.n_pad));
   HIPTRY(h->dalloc(&h->L32, (size_t)ix.kmax * ix.n_pad));
-  HIPTRY(h->dalloc(&h->LB, (size_t)ix.kmax * ix.nB));
-  HIPTRY(h->dalloc(&h->bnorm, (size_t)ix.nB));
+  HIPTRY(h->dalloc(&h->LB, (size_t)ix.kmax * ix.nSB));
+  HIPTRY(h->dalloc(&h->bnorm, (size_t)ix.nSB));
   ix.L64 = h->L64;
   ix.L32 = h->L32;
   ix.LB = h->LB;
@@ -337,6 +338,9 @@ rk_status build_impl(const float* Q, int64_t n, const float* P, int64_t m, int32
   ix.kmax = k_max;
   ix.nB = (int32_t)(ix.n_pad / TILE);
   ix.mB = (int32_t)(ix.m_pad / TILE);
+  ix.bsize = o.block_size ? o.block_size : TILE;
+  ix.nSB = (int32_t)(ix.n_pad / ix.bsize);
+  ix.use_blocks = o.no_blocks ? 0 : 1;
   const int64_t lb = (o.lb_items == 0 || o.lb_items >= m) ? m : o.lb_items;
   ix.lb_items = (int32_t)lb;
   ix.exact = (lb == m) ? 1 : 0;
@@ -1342,7 +1346,7 @@ rk_status rk_index_stats(const rk_index* hc, rk_stats* o) {
   std::memset(o, 0, sizeof(*o));
   const DevIndex& ix = h->ix;
   o->n = ix.n; o->m = ix.m; o->d = ix.d; o->k_max = ix.kmax; o->lb_items = ix.lb_items;
-  o->block_size = TILE; o->n_blocks = ix.nB; o->precision = ix.bf16 ? RK_BF16 : RK_FP32;
+  o->block_size = ix.bsize; o->n_blocks = ix.nSB; o->precision = ix.bf16 ? RK_BF16 : RK_FP32;
   o->footprint_bytes = (int64_t)h->footprint + h->bw.bytes;
   o->build_ms = h->build_ms;
   o->build_cand_total = h->cand_total;
@@ -1375,8 +1379,8 @@ rk_status rk_index_export(const rk_index* hc, int32_t field, void* dst, int64_t 
     case RK_F_NORM_P: src = h->normP; need = ix.m * 4; break;
     case RK_F_L64: src = h->L64; rows = ix.kmax; width = ix.n * 8; pitch = ix.n_pad * 8; break;
     case RK_F_L32: src = h->L32; rows = ix.kmax; width = ix.n * 4; pitch = ix.n_pad * 4; break;
-    case RK_F_LB: src = h->LB; need = (int64_t)ix.kmax * ix.nB * 4; break;
-    case RK_F_BNORM: src = h->bnorm; need = (int64_t)ix.nB * 4; break;
+    case RK_F_LB: src = h->LB; need = (int64_t)ix.kmax * ix.nSB * 4; break;
+    case RK_F_BNORM: src = h->bnorm; need = (int64_t)ix.nSB * 4; break;
     default: return fail(RK_E_INVAL, "unknown field");
   }
   if (rows) need = rows * width;
@@ -1397,7 +1401,8 @@ int64_t rk_index_footprint(int64_t n, int64_t m, int32_t d, int32_t k_max, const
   rk_build_opts_default(&o);
   if (opts) o = *opts;
   if (n < 0 || m < 0 || d < 1 || k_max < 1) return -1;
-  const int64_t np = round_up(n, TILE), mp = round_up(m, TILE), nB = np / TILE;
+  const int64_t np = round_up(n, TILE), mp = round_up(m, TILE);
+  const int64_t nB = np / (o.block_size == 16 || o.block_size == 32 ? o.block_size : TILE);
   const int64_t d16 = round_up(d, 16);
   int64_t b = 0;
   b += n * 8 + m * 8 + n * 4 + m * 4;                 // squared norms, permutations
