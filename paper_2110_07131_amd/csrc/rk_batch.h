@@ -4,13 +4,6 @@
 
 namespace rk {
 
-constexpr int kBatchChunkMax = 4096;  // queries per chunk (single-workgroup sort in LDS)
-constexpr int kPairChunk = 256;       // slots per pair chunk (bounded table)
-constexpr int kUserPairs = 8;         // flagged-pair slots per user in the scan's long pass
-constexpr int kExactRun = 64;         // exact table: pair slots a filter wave reserves at a time
-
-// Scan list length per user: k_max + 2 rounded up to a multiple of 4.
-__host__ __device__ inline int bscan_list_len(int kmax) { return (kmax + 2 + 3) / 4 * 4; }
 
 struct BatchView {
   const float* qs;              // chunk queries [nq][d], caller order

@@ -14,11 +14,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "host_rules.h"
 #include "rkmips.h"
 
 namespace rk {
-
-constexpr int TILE = 64;  // users per block == items per tile == wave size
 
 __host__ __device__ inline int64_t tix(int64_t r, int c, int d) {
   return (r / TILE) * (int64_t)d * TILE + (int64_t)c * TILE + (r % TILE);

@@ -39,27 +39,6 @@ rk_status fail(rk_status st, const std::string& msg) {
   } while (0)
 
 constexpr int64_t kSeedItems = 1024;  // exact float64 prefix that seeds the full build
-constexpr int32_t kMaxD = 512;
-constexpr int32_t kMaxKmax = 128;
-
-int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
-
-// Words of a batched result bitmap row: one bit per user, rows 16-byte aligned.
-int64_t bitmap_words(int64_t n) { return round_up(std::max<int64_t>((n + 31) / 32, 1), 4); }
-
-double gamma_(double k, double u) { return k * u / (1.0 - k * u); }
-
-// Rigorous relative bounds |approx u.x - f(x,u)| <= eps * |u| |x| (see the
-// error analysis in the design notes): float32 accumulation of d exact or
-// once-rounded products in any order, plus the float64 rounding of f itself,
-// plus slack for evaluating the certified tests in float32.
-double eps_fp32(int d) {
-  return gamma_(d + 2, 0x1p-24) + gamma_(d, 0x1p-53) + 16 * 0x1p-24;
-}
-double eps_bf16(int d) {
-  const double r = (1 + 0x1p-8) * (1 + 0x1p-8) * (1 + gamma_(d + 2, 0x1p-24)) - 1;
-  return r + gamma_(d, 0x1p-53) + 16 * 0x1p-24;
-}
 
 // Device workspace of the batched path for chunks of up to qcap queries
 // (grown on demand).  An index owns one for its own calls; every serving slot
@@ -200,32 +179,16 @@ struct rk_index {
 namespace {
 
 rk_status check_opts(const rk_build_opts& o) {
-  if (o.precision != RK_FP32 && o.precision != RK_BF16) return fail(RK_E_INVAL, "precision must be RK_FP32 or RK_BF16");
-  if (o.lb_items < 0) return fail(RK_E_INVAL, "lb_items must be >= 0");
-  if (o.block_size != 0 && o.block_size != 16 && o.block_size != 32 && o.block_size != TILE)
-    return fail(RK_E_INVAL, "block_size must be 0, 16, 32 or 64");
-  if (!(o.margin_rel >= 0.0) || !std::isfinite(o.margin_rel) || o.margin_rel >= 0.5)
-    return fail(RK_E_INVAL, "margin_rel must be finite, >= 0 and < 0.5");
-  if (o.cand_cap < 0) return fail(RK_E_INVAL, "cand_cap must be >= 0");
-  if (o.pair_cap < 0) return fail(RK_E_INVAL, "pair_cap must be >= 0");
-  if (o.handoff_tiles < 0) return fail(RK_E_INVAL, "handoff_tiles must be >= 0");
-  if (o.device < 0) return fail(RK_E_INVAL, "device must be >= 0");
-  return RK_OK;
+  const char* e = opts_error(o);
+  return e ? fail(RK_E_INVAL, e) : RK_OK;
 }
 
 rk_status check_sizes(int64_t n, int64_t m, int32_t d, int32_t k_max) {
-  if (n < 0 || m < 0) return fail(RK_E_INVAL, "n and m must be >= 0");
-  if (n > INT32_MAX - 64 || m > INT32_MAX - 64) return fail(RK_E_INVAL, "n and m must fit int32 ids");
-  if (d < 1 || d > kMaxD) return fail(RK_E_INVAL, "d must be in [1, 512]");
-  if (k_max < 1 || k_max > kMaxKmax) return fail(RK_E_INVAL, "k_max must be in [1, 128]");
-  return RK_OK;
+  const char* e = sizes_error(n, m, d, k_max);
+  return e ? fail(RK_E_INVAL, e) : RK_OK;
 }
 
-bool host_values_ok(const float* x, int64_t count) {
-  for (int64_t i = 0; i < count; ++i)
-    if (!(std::fabs(x[i]) < 1099511627776.0f)) return false;
-  return true;
-}
+bool host_values_ok(const float* x, int64_t count) { return values_ok(x, count); }
 
 // Build the lower-bound arrays and blocks for the index's current k_max from
 // the sorted device copies (Algorithm 1, lower-bound arrays and blocks).
@@ -537,67 +500,25 @@ rk_status check_batch_ks(rk_index* h, const int32_t* ks, int64_t nq) {
   return RK_OK;
 }
 
-constexpr int64_t kBitmapBudget = 512ll << 20;  // bytes of per-query result bits per chunk
-// Undecided-pair slots per chunk of queries.  Exact table: only the pairs
-// within rounding of theta_k (rechecks); bounded table: every survivor of the
-// filter goes to the scan.
-constexpr int64_t kPairBudgetExact = 1ll << 24;
-constexpr int64_t kPairBudget = 1ll << 27;
 constexpr size_t kMaxLds = 160 * 1024;
 
-// Sizes of the batched path's workspace for chunks of `chunk` queries.
-struct BatchSizes {
-  int64_t pc = 0;         // pair slots
-  int64_t chunk_cap = 0;  // pair chunks (bounded table)
-  int64_t maxc = 0;       // chunk-list capacity per block (bounded table)
-  int64_t bytes = 0;      // device bytes of the whole workspace
-};
-
-BatchSizes batch_sizes(const rk_index* h, int32_t chunk) {
-  const DevIndex& ix = h->ix;
-  BatchSizes z;
-  const int64_t cp = round_up(chunk, TILE), W = bitmap_words(ix.n);
-  int64_t pc = std::min<int64_t>((int64_t)chunk * std::max<int64_t>(ix.n_pad, 1),
-                                 ix.exact ? kPairBudgetExact : kPairBudget);
-  // exact table: each of a block's four filter waves may leave up to
-  // kExactRun - 1 slots of its last reserved run unused
-  // (bounded so that very large catalogs keep a modest list)
-  if (ix.exact) pc += std::min<int64_t>(4 * (int64_t)ix.nB * kExactRun, 3 * kPairBudgetExact);
-  if (h->opts.pair_cap > 0) pc = h->opts.pair_cap;
-  if (!ix.exact) {
-    // Chunks of kPairChunk slots: every chunk is full but the one each of a
-    // block's four filter waves is filling, so pc pairs need at most
-    // pc / kPairChunk + 4 nB chunks (an explicit pair_cap is taken as is).
-    z.chunk_cap = h->opts.pair_cap > 0 ? pc / kPairChunk
-                                       : (pc + kPairChunk - 1) / kPairChunk + 4 * (int64_t)ix.nB;
-    z.chunk_cap = std::min<int64_t>(z.chunk_cap, INT32_MAX / kPairChunk);
-    pc = std::max<int64_t>(pc, z.chunk_cap * kPairChunk);
-    z.maxc = TILE * cp / kPairChunk + 4;
-  }
-  z.pc = pc;
-  const int64_t d2 = ix.d + (ix.d & 1);
-  int64_t b = chunk * 4 * 2 + cp * d2 * 4 + (ix.bf16 ? cp * ix.d16 * 2 : 0) + cp * 12 +
-              chunk * W * 4 + chunk * 8 + chunk + 8 + pc * 12 + chunk * 4;
-  if (!ix.exact)
-    b += std::max<int64_t>(pc, 1) * 4 + std::max<int64_t>(z.chunk_cap, 1) * 4 + 4 +
-         std::max<int64_t>(ix.nB, 1) * 4 * (1 + z.maxc) +
-         std::max<int64_t>(ix.n_pad, 1) * (8 * (int64_t)bscan_list_len(ix.kmax) + 4) + 4 +
-         std::max<int64_t>(ix.nB, 1) * 4 + std::max<int64_t>(ix.n_pad, 1) * (20 + 12 * kUserPairs) + 4;
-  z.bytes = b;
-  return z;
+BatchShape shape_of(const rk_index* h) {
+  BatchShape x;
+  x.n = h->ix.n;
+  x.n_pad = h->ix.n_pad;
+  x.nB = h->ix.nB;
+  x.d = h->ix.d;
+  x.d16 = h->ix.d16;
+  x.kmax = h->ix.kmax;
+  x.exact = h->ix.exact != 0;
+  x.bf16 = h->ix.bf16 != 0;
+  x.pair_cap_opt = h->opts.pair_cap;
+  return x;
 }
 
-// Queries per chunk of the batched path for a batch of nq queries.  With a
-// bounded table every survivor of the filter takes a pair slot; the chunk is
-// sized so that up to a quarter of all (user, query) pairs fit the slots (a
-// larger share would spill into the filter's in-kernel float64 fallback).
-int32_t batch_chunk(const rk_index* h, int64_t nq) {
-  const int64_t W = bitmap_words(h->ix.n);
-  int64_t c = std::min<int64_t>({nq, (int64_t)kBatchChunkMax, kBitmapBudget / (W * 4)});
-  if (!h->ix.exact && h->opts.pair_cap == 0)
-    c = std::min<int64_t>(c, std::max<int64_t>(TILE, kPairBudget / std::max<int64_t>(h->ix.n_pad / 4, 1)));
-  return (int32_t)std::max<int64_t>(1, c);
-}
+BatchSizes batch_sizes(const rk_index* h, int32_t chunk) { return batch_sizes(shape_of(h), chunk); }
+
+int32_t batch_chunk(const rk_index* h, int64_t nq) { return batch_chunk(shape_of(h), nq); }
 
 rk_status ensure_batch_ws(rk_index* h, BatchWS& b, int32_t chunk, hipStream_t s) {
   if (b.qcap >= chunk) return RK_OK;
@@ -772,41 +693,28 @@ rk_status scratch_for(int device, unsigned char** out) {
   return RK_OK;
 }
 
-// Lays out the exact-table batch workspace for chunks of `chunk` queries in
-// [base, base + bytes), pair slots last with whatever is left (at most the
-// regular budget; pairs beyond them are decided in float64 by the filter).
-// Returns the bytes the layout needs without pair slots (> bytes: no fit).
-size_t carve_ws(const rk_index* h, BatchWS& b, int32_t chunk, unsigned char* base, size_t bytes) {
-  const DevIndex& ix = h->ix;
-  const int64_t cp = round_up(chunk, TILE), W = bitmap_words(ix.n);
-  size_t off = 0;
-  auto take = [&](auto** p, int64_t count) {
-    off = (size_t)round_up((int64_t)off, 256);
-    *p = reinterpret_cast<std::remove_reference_t<decltype(**p)>*>(base + off);
-    off += (size_t)std::max<int64_t>(count, 1) * sizeof(**p);
-  };
+// Points the workspace b at the layout of chunks of `chunk` queries inside
+// the static array at base.
+void carve_ws(const rk_index* h, BatchWS& b, int32_t chunk, unsigned char* base, size_t bytes) {
+  const ScratchLayout L = scratch_layout(shape_of(h), chunk, bytes);
   b = BatchWS();
-  take(&b.bits, (int64_t)chunk * std::max<int64_t>(W, 1));
-  take(&b.counts, chunk);
-  take(&b.qn, chunk);
-  take(&b.perm, chunk);
-  take(&b.qt, cp * (ix.d + (ix.d & 1)));
-  if (ix.bf16) take(&b.qb, cp * ix.d16);
-  take(&b.qn_s, cp);
-  take(&b.k_s, cp);
-  take(&b.kofs_s, cp);
-  take(&b.all, chunk);
-  take(&b.npairs, 1);
-  take(&b.ks_dev, chunk);
-  const size_t fixed = off;
-  const size_t left = bytes > fixed + 4 * 256 ? bytes - fixed - 4 * 256 : 0;
-  const int64_t pc = std::min<int64_t>(batch_sizes(h, chunk).pc, (int64_t)(left / 12));
-  take(&b.pair_u, pc);
-  take(&b.pair_j, pc);
-  take(&b.pair_s, pc);
-  b.pair_cap = pc;
+  b.bits = (uint32_t*)(base + L.bits);
+  b.counts = (unsigned long long*)(base + L.counts);
+  b.qn = (float*)(base + L.qn);
+  b.perm = (int32_t*)(base + L.perm);
+  b.qt = (float*)(base + L.qt);
+  b.qb = h->ix.bf16 ? (uint16_t*)(base + L.qb) : nullptr;
+  b.qn_s = (float*)(base + L.qn_s);
+  b.k_s = (int32_t*)(base + L.k_s);
+  b.kofs_s = (int32_t*)(base + L.kofs_s);
+  b.all = (uint8_t*)(base + L.all);
+  b.npairs = (unsigned long long*)(base + L.npairs);
+  b.ks_dev = (int32_t*)(base + L.ks);
+  b.pair_u = (int32_t*)(base + L.pair_u);
+  b.pair_j = (int32_t*)(base + L.pair_j);
+  b.pair_s = (float*)(base + L.pair_s);
+  b.pair_cap = L.pc;
   b.qcap = chunk;
-  return fixed;
 }
 
 }  // namespace
@@ -848,14 +756,6 @@ struct ServerSlot {
   int32_t* ids_pin = nullptr;
   std::thread worker;
 };
-
-// Launch-time estimates per batch-size bucket (ceil(log2(nq)), 0..15).
-constexpr int kSizeBuckets = 16;
-inline int size_bucket(int64_t nq) {
-  int b = 0;
-  while (b < kSizeBuckets - 1 && (int64_t(1) << b) < nq) ++b;
-  return b;
-}
 
 struct ServerCatalog {
   rk_index* idx = nullptr;
@@ -1240,17 +1140,12 @@ rk_status rk_reverse_kmips_batch_dev_noalloc(rk_index* h, const float* qs_dev, i
   }
   // the largest chunk (a power-of-two fraction of the regular one, at least
   // 64 queries) whose workspace fits with room for 64 Ki pair slots
-  int32_t chunk = batch_chunk(h, nq);
+  const int32_t chunk = noalloc_chunk(shape_of(h), nq, kScratchBytes);
+  if (chunk == 0)
+    return fail(RK_E_INVAL, "noalloc batch: " + std::to_string(ix.n) + " users need more than the " +
+                                std::to_string(kScratchBytes >> 20) + " MiB static workspace");
   BatchWS b;
-  for (;;) {
-    const size_t fixed = carve_ws(h, b, chunk, base, kScratchBytes);
-    const int64_t want_pairs = std::min<int64_t>(batch_sizes(h, chunk).pc, 1 << 16);
-    if (fixed + 4 * 256 + (size_t)want_pairs * 12 <= kScratchBytes) break;
-    if (chunk <= TILE)
-      return fail(RK_E_INVAL, "noalloc batch: " + std::to_string(ix.n) + " users need more than the " +
-                                  std::to_string(kScratchBytes >> 20) + " MiB static workspace");
-    chunk = std::max<int32_t>(TILE, chunk / 2);
-  }
+  carve_ws(h, b, chunk, base, kScratchBytes);
   // the array keeps the last call's contents: result bits and counts must
   // start at zero (the assembly clears them again after each chunk)
   const int64_t W = bitmap_words(ix.n);
@@ -1400,17 +1295,7 @@ int64_t rk_index_footprint(int64_t n, int64_t m, int32_t d, int32_t k_max, const
   rk_build_opts o;
   rk_build_opts_default(&o);
   if (opts) o = *opts;
-  if (n < 0 || m < 0 || d < 1 || k_max < 1) return -1;
-  const int64_t np = round_up(n, TILE), mp = round_up(m, TILE);
-  const int64_t nB = np / (o.block_size == 16 || o.block_size == 32 ? o.block_size : TILE);
-  const int64_t d16 = round_up(d, 16);
-  int64_t b = 0;
-  b += n * 8 + m * 8 + n * 4 + m * 4;                 // squared norms, permutations
-  b += np * d * 4 + np * 4 + mp * d * 4 + mp * 4 + m * d * 4 + n * d * 4;  // tiled copies, norms, rows
-  if (o.precision == RK_BF16) b += (np + mp) * d16 * 2;
-  b += (int64_t)k_max * np * 12 + (int64_t)k_max * nB * 4 + nB * 4;  // L64, L32, LB, bnorm
-  b += ((n + 31) / 32) * 4 + np * 12 + 4 * 4 + 4 + 16 * 8 + d * 4 + std::max<int64_t>(n, 1) * 4 + 8;
-  return b;
+  return index_footprint(n, m, d, k_max, o);
 }
 
 void rk_server_opts_default(rk_server_opts* o) {
