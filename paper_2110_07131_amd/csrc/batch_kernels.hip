@@ -137,6 +137,34 @@ __global__ void k_btile(const float* __restrict__ qs, const int32_t* __restrict_
   }
 }
 
+// Per tile of sorted queries and per query half (rows 32 h .. 32 h + 31): the
+// largest norm (float bits), the smallest and largest k row, and the first
+// row of the largest k when the half holds at most two k's (0 for one k; -1
+// for more).  Rows are sorted by k, so with two k's every live row from that
+// row on has the larger one (rows of k > m or padding, which hold row 0,
+// come last and are never live).  One wave per tile.
+__global__ void k_btsum(const float* __restrict__ qn_s, const int32_t* __restrict__ kofs_s,
+                        int32_t* __restrict__ tsum) {
+  const int64_t T = blockIdx.x;
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  const float n = qn_s[T * TILE + lane];
+  const int k = kofs_s[T * TILE + lane];
+  float nmax = n;
+  int kmin = k, kmx = k;
+  for (int off = 16; off > 0; off >>= 1) {  // within each half of the wave
+    nmax = fmaxf(nmax, __shfl_xor(nmax, off));
+    kmin = min(kmin, __shfl_xor(kmin, off));
+    kmx = max(kmx, __shfl_xor(kmx, off));
+  }
+  const uint32_t other = (uint32_t)(__ballot(k != kmin && k != kmx) >> (32 * h));
+  const uint32_t hi = (uint32_t)(__ballot(k == kmx) >> (32 * h));
+  const int code = kmin == kmx ? 0 : (other ? -1 : __ffs((int)hi) - 1);
+  if ((lane & 31) < 4) {
+    const int v[4] = {__float_as_int(nmax), kmin, kmx, code};
+    tsum[T * 8 + 4 * h + (lane & 31)] = v[lane & 31];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Exact float64 decision of one (user, query) pair, used by a lane whose
 // undecided pair does not fit the pair list: with an exact table f(q,u)
@@ -198,6 +226,7 @@ __device__ __forceinline__ void stage_tile(const u32x4* __restrict__ qsrc, const
   }
   if (t < TILE) pf_n = bv.qn_s[(int64_t)T * TILE + t];
   else if (t < 2 * TILE) pf_k = bv.kofs_s[(int64_t)T * TILE + t - TILE];
+  else if (t < 2 * TILE + 8) pf_k = bv.tsum[(int64_t)T * 8 + t - 2 * TILE];
 }
 
 template <int NV>
@@ -211,7 +240,7 @@ __device__ __forceinline__ void commit_tile(unsigned char* qbuf, float* meta_n, 
     if (lo_half<NV>(v) || i < tile_vecs) dst[i] = pf[v];
   }
   if (t < TILE) meta_n[t] = pf_n;
-  else if (t < 2 * TILE) meta_k[t - TILE] = pf_k;
+  else if (t < 2 * TILE + 8) meta_k[t - TILE] = pf_k;  // k rows, then the 8 summary words
 }
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -236,6 +265,9 @@ __device__ __forceinline__ void issue_tile(const unsigned char* __restrict__ qsr
   else if (wave == 1)
     __builtin_amdgcn_global_load_lds((const void*)(bv.kofs_s + (int64_t)T * TILE + lane),
                                      (lds_void_t*)mk_dst, 4, 0, 0);
+  else if (wave == 2 && lane < 8)
+    __builtin_amdgcn_global_load_lds((const void*)(bv.tsum + (int64_t)T * 8 + lane),
+                                     (lds_void_t*)(mk_dst + TILE), 4, 0, 0);
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave in registers (DPP): the
@@ -289,8 +321,9 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   if (LDSD) p += (tile_bytes + 15) / 16 * 16;
   float* meta_n2 = (float*)p;    // [2][64] norms of the tile's queries
   p += 2 * TILE * 4;
-  int32_t* meta_k2 = (int32_t*)p;  // [2][64] their k's rows in the (k, user) tables
-  p += 2 * TILE * 4;
+  int32_t* meta_k2 = (int32_t*)p;  // [2][72] their k's rows in the (k, user) tables, and
+                                   // the tile's two half summaries (k_btsum)
+  p += 2 * (TILE + 8) * 4;
   // Lemma 3 blocks of bsize users: nsb per 64-user tile, a live-query mask
   // per (block, query tile), and with nsb > 1 their union (the tile walk)
   constexpr int MT = kBatchChunkMax / TILE;
@@ -402,10 +435,11 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
     // this one is used
     if (LDSD && Tn < nT)
       issue_tile(qsrc, bv, Tn, tile_bytes, lane, wave, qbuf2[slot ^ 1], meta_n2 + (slot ^ 1) * TILE,
-                 meta_k2 + (slot ^ 1) * TILE);
-    const unsigned char* qbuf = qbuf2[slot];
+                 meta_k2 + (slot ^ 1) * (TILE + 8));
+    // (offset from one base, not an array of pointers: the reads stay LDS reads)
+    const unsigned char* qbuf = qbuf2[0] + (LDSD ? slot * (int)(qbuf2[1] - qbuf2[0]) : 0);
     const float* meta_n = meta_n2 + slot * TILE;
-    const int32_t* meta_k = meta_k2 + slot * TILE;
+    const int32_t* meta_k = meta_k2 + slot * (TILE + 8);
     const unsigned long long mask = walk[T];
     // this wave's query half may have no live query at all
     const uint32_t hmask = (uint32_t)(mask >> (qhalf * 32));
@@ -445,185 +479,218 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qv[2 * ks * TILE], uv[2 * ks * TILE], acc, 0, 0, 0);
     }
 
-    // ---- certified tests.  Lemma 1: "no" iff s + e < L.  "Yes" iff
-    // s - e >= Y, with Y the float above L (exact table: f >= theta_k) or
-    // the Cauchy-Schwarz bound of the k-th item (Lemma 2), both per (k,
-    // user) in LDS.  e = eps|u||q| + eps_abs; both tests round relative to
-    // |u||q|, which the slack inside eps covers.
-    // the lane's rows are qhalf*32 + g*8 + half*4 + i  (r = 4g + i)
-    // the rows live for this lane's own block (blocks of fewer than 64 users)
-    const uint32_t hm = (nsb > 1 ? (uint32_t)(masks[((uh * 32 + col) / ix.bsize) * MT + T] >> (qhalf * 32))
-                                 : hmask) >> (half * 4);
-    const uint32_t cells = (hm & 0xFu) | ((hm >> 4) & 0xF0u) | ((hm >> 8) & 0xF00u) |
-                           ((hm >> 12) & 0xF000u);
-    const int ucol = uh * 32 + col;
-    uint32_t rest = 0;
+    // ---- conservative Lemma 1 pass with the tile half's summary (k_btsum):
+    // the largest query norm's margin and one or two lower bounds per user,
+    // two vector operations per pair.  It rejects only what the exact test
+    // below rejects; the exact tests run only for a wave with a pair it does
+    // not reject (or that counts statistics).  Used for tiles of d = 65-128
+    // (NV = 4 in bf16, 8 in float32), where it measured 5% faster in both
+    // precisions at d = 100; at d = 50 its registers cost the bf16 filter a
+    // wave per SIMD (6-7% slower in both precisions), and at d = 200 with k ~
+    // U{1..50} too many tile halves hold several k's (2-9% slower).
+    constexpr bool FASTL1 = BF16 ? NV == 4 : NV == 8;
+    bool flag = true;
+    if constexpr (FASTL1) {
+      const int4 sm = *(const int4*)(meta_k + TILE + 4 * qhalf);
+      const int uc = uh * 32 + col;
+      const float e = fmaf(a_u, __int_as_float(sm.x), ix.eps_abs);
+      const float Lhi = Ll[sm.z + uc];
+      if (sm.w == 0) {
+        bool fl = false;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int rb = quarter_row(qhalf, half, g * 4);
-      const float4 n4 = *(const float4*)(meta_n + rb);
-      const int4 k4 = *(const int4*)(meta_k + rb);
-      const float nqs[4] = {n4.x, n4.y, n4.z, n4.w};
-      const int kks[4] = {k4.x, k4.y, k4.z, k4.w};
+        for (int r = 0; r < 16; ++r) fl |= !(acc[r] + e < Lhi);
+        flag = fl;
+      } else if (sm.w > 0) {
+        const float Llo = Ll[sm.y + uc];
+        bool fl = false;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = g * 4 + i;
-        const float ev = fmaf(a_u, nqs[i], ix.eps_abs);
-        const float L = Ll[kks[i] + ucol];
-        rest |= (uint32_t)!(acc[r] + ev < L) << r;
+        for (int r = 0; r < 16; ++r)
+          fl |= !(acc[r] + e < ((r / 4) * 8 + half * 4 + (r % 4) >= sm.w ? Lhi : Llo));
+        flag = fl;
       }
+      flag = flag && valid;
     }
-    rest &= valid ? cells : 0u;
-    uint32_t yes = 0;
-    if (__ballot(rest != 0u)) {  // some pair Lemma 1 did not reject: the "yes" test
-      // small float32 tiles: the rows' norms and k's are read again here
-      // instead of held in registers since the Lemma 1 test (an opaque row
-      // offset keeps the compiler from reusing those loads), so that the
-      // 4-wave register budget needs no spill: a spilled address reloaded
-      // before the products waited for the next tile's loads (5% faster).
-      // Larger tiles keep them (1-2% faster).
-      int rq = quarter_row(qhalf, half, 0);
-      if constexpr (!BF16 && NV <= 4) asm volatile("" : "+v"(rq));
-#pragma unroll
+    if (!FASTL1 || bv.ctr || __ballot(flag)) {
+      // ---- certified tests.  Lemma 1: "no" iff s + e < L.  "Yes" iff
+      // s - e >= Y, with Y the float above L (exact table: f >= theta_k) or
+      // the Cauchy-Schwarz bound of the k-th item (Lemma 2), both per (k,
+      // user) in LDS.  e = eps|u||q| + eps_abs; both tests round relative to
+      // |u||q|, which the slack inside eps covers.
+      // the lane's rows are qhalf*32 + g*8 + half*4 + i  (r = 4g + i)
+      // the rows live for this lane's own block (blocks of fewer than 64 users)
+      const uint32_t hm = (nsb > 1 ? (uint32_t)(masks[((uh * 32 + col) / ix.bsize) * MT + T] >> (qhalf * 32))
+                                   : hmask) >> (half * 4);
+      const uint32_t cells = (hm & 0xFu) | ((hm >> 4) & 0xF0u) | ((hm >> 8) & 0xF00u) |
+                             ((hm >> 12) & 0xF000u);
+      const int ucol = uh * 32 + col;
+      uint32_t rest = 0;
+  #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const int rb = rq + g * 8;
+        const int rb = quarter_row(qhalf, half, g * 4);
         const float4 n4 = *(const float4*)(meta_n + rb);
         const int4 k4 = *(const int4*)(meta_k + rb);
         const float nqs[4] = {n4.x, n4.y, n4.z, n4.w};
         const int kks[4] = {k4.x, k4.y, k4.z, k4.w};
-#pragma unroll
+  #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int r = g * 4 + i;
           const float ev = fmaf(a_u, nqs[i], ix.eps_abs);
-          const float Y = Yl[kks[i] + ucol];
-          yes |= (uint32_t)(acc[r] - ev >= Y) << r;
+          const float L = Ll[kks[i] + ucol];
+          rest |= (uint32_t)!(acc[r] + ev < L) << r;
         }
       }
-      yes &= rest;
-    }
-    const uint32_t und = rest & ~yes;
-    if (bv.ctr) {
-      c_users += valid ? __popc(cells) : 0;
-      c_rest += __popc(rest);
-      c_yes += __popc(yes);
-    }
-    // ---- certified members: result bits
-    uint32_t yy = yes;
-    while (yy) {
-      const int r = __ffs(yy) - 1;
-      yy &= yy - 1;
-      const int32_t jo = bv.perm[(int64_t)T * TILE + quarter_row(qhalf, half, r)];
-      atomicOr(&bv.bits[(int64_t)jo * bv.W + (orig_u >> 5)], 1u << (orig_u & 31));
-      atomicAdd(&bv.counts[jo], 1ull);
-    }
-    // ---- undecided pairs: appended (one atomic per wave).  Exact table:
-    // one flat list.  Bounded table: the wave fills chunks of its own, each
-    // registered in the block's chunk list, so that the scan finds the
-    // block's pairs together.
-    if (__ballot(und != 0u)) {
-      const int cnt = __popc(und);
-      const int incl = wave_incl_scan(cnt);
-      uint32_t ovf = 0;  // pairs beyond the list's capacity
-      if (ix.exact) {
-        // slots come from the wave's run of reserved slots, and a new run
-        // only when it is used up: the returning atomic's wait covers every
-        // load in flight, the next tile's prefetch included (vector memory
-        // returns in order), so one per tile with such pairs cost the bf16
-        // filter 11-21%
-        const int total = __builtin_amdgcn_readlane(incl, 63);
-        const int avail = erun - efill;
-        int need = 0;
-        int64_t nb = 0;
-        if (total > avail) {
-          need = (total - avail + kExactRun - 1) / kExactRun * kExactRun;
-          unsigned long long got = 0;
-          if (lane == 0) got = atomicAdd(bv.npairs, (unsigned long long)need);
-          const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)got, 0);
-          const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(got >> 32), 0);
-          nb = (int64_t)(((uint64_t)hi << 32) | lo);
-        }
-        int p = incl - cnt;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          if ((und >> r) & 1u) {
-            const int64_t pos = p < avail ? erun0 + efill + p : nb + (p - avail);
-            ++p;
-            if (pos < bv.pair_cap) {
-              bv.pair_u[pos] = (int32_t)u;
-              bv.pair_j[pos] = (int32_t)((int64_t)T * TILE + quarter_row(qhalf, half, r));
-              bv.pair_s[pos] = acc[r];
-            } else {
-              ovf |= 1u << r;
-            }
+      rest &= valid ? cells : 0u;
+      uint32_t yes = 0;
+      if (__ballot(rest != 0u)) {  // some pair Lemma 1 did not reject: the "yes" test
+        // small float32 tiles: the rows' norms and k's are read again here
+        // instead of held in registers since the Lemma 1 test (an opaque row
+        // offset keeps the compiler from reusing those loads), so that the
+        // 4-wave register budget needs no spill: a spilled address reloaded
+        // before the products waited for the next tile's loads (5% faster).
+        // Larger tiles keep them (1-2% faster).
+        int rq = quarter_row(qhalf, half, 0);
+        if constexpr (!BF16 && NV <= 4) asm volatile("" : "+v"(rq));
+  #pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int rb = rq + g * 8;
+          const float4 n4 = *(const float4*)(meta_n + rb);
+          const int4 k4 = *(const int4*)(meta_k + rb);
+          const float nqs[4] = {n4.x, n4.y, n4.z, n4.w};
+          const int kks[4] = {k4.x, k4.y, k4.z, k4.w};
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = g * 4 + i;
+            const float ev = fmaf(a_u, nqs[i], ix.eps_abs);
+            const float Y = Yl[kks[i] + ucol];
+            yes |= (uint32_t)(acc[r] - ev >= Y) << r;
           }
         }
-        if (need > 0) {
-          erun0 = nb;
-          erun = need;
-          efill = total - avail;
+        yes &= rest;
+      }
+      const uint32_t und = rest & ~yes;
+      if (bv.ctr) {
+        c_users += valid ? __popc(cells) : 0;
+        c_rest += __popc(rest);
+        c_yes += __popc(yes);
+      }
+      // ---- certified members: result bits
+      uint32_t yy = yes;
+      while (yy) {
+        const int r = __ffs(yy) - 1;
+        yy &= yy - 1;
+        const int32_t jo = bv.perm[(int64_t)T * TILE + quarter_row(qhalf, half, r)];
+        atomicOr(&bv.bits[(int64_t)jo * bv.W + (orig_u >> 5)], 1u << (orig_u & 31));
+        atomicAdd(&bv.counts[jo], 1ull);
+      }
+      // ---- undecided pairs: appended (one atomic per wave).  Exact table:
+      // one flat list.  Bounded table: the wave fills chunks of its own, each
+      // registered in the block's chunk list, so that the scan finds the
+      // block's pairs together.
+      if (__ballot(und != 0u)) {
+        const int cnt = __popc(und);
+        const int incl = wave_incl_scan(cnt);
+        uint32_t ovf = 0;  // pairs beyond the list's capacity
+        if (ix.exact) {
+          // slots come from the wave's run of reserved slots, and a new run
+          // only when it is used up: the returning atomic's wait covers every
+          // load in flight, the next tile's prefetch included (vector memory
+          // returns in order), so one per tile with such pairs cost the bf16
+          // filter 11-21%
+          const int total = __builtin_amdgcn_readlane(incl, 63);
+          const int avail = erun - efill;
+          int need = 0;
+          int64_t nb = 0;
+          if (total > avail) {
+            need = (total - avail + kExactRun - 1) / kExactRun * kExactRun;
+            unsigned long long got = 0;
+            if (lane == 0) got = atomicAdd(bv.npairs, (unsigned long long)need);
+            const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)got, 0);
+            const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(got >> 32), 0);
+            nb = (int64_t)(((uint64_t)hi << 32) | lo);
+          }
+          int p = incl - cnt;
+  #pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            if ((und >> r) & 1u) {
+              const int64_t pos = p < avail ? erun0 + efill + p : nb + (p - avail);
+              ++p;
+              if (pos < bv.pair_cap) {
+                bv.pair_u[pos] = (int32_t)u;
+                bv.pair_j[pos] = (int32_t)((int64_t)T * TILE + quarter_row(qhalf, half, r));
+                bv.pair_s[pos] = acc[r];
+              } else {
+                ovf |= 1u << r;
+              }
+            }
+          }
+          if (need > 0) {
+            erun0 = nb;
+            erun = need;
+            efill = total - avail;
+          } else {
+            efill += total;
+          }
         } else {
-          efill += total;
-        }
-      } else {
-        const int total = __builtin_amdgcn_readlane(incl, 63);
-        const int avail = kPairChunk - cfill_w;  // free slots of the current chunk
-        const int need = total > avail ? (total - avail + kPairChunk - 1) / kPairChunk : 0;
-        int nb = 0;
-        if (need > 0) {
-          if (lane == 0) nb = atomicAdd(bv.nchunks, need);
-          nb = __builtin_amdgcn_readlane(nb, 0);
-          if (lane < need && nb + lane < bv.chunk_cap) {
-            bv.cfill[nb + lane] = kPairChunk;  // the last one is corrected at the end
-            const int at = atomicAdd(&bv.bcnt[B], 1);
-            bv.bchunks[B * bv.maxc + at] = nb + lane;
+          const int total = __builtin_amdgcn_readlane(incl, 63);
+          const int avail = kPairChunk - cfill_w;  // free slots of the current chunk
+          const int need = total > avail ? (total - avail + kPairChunk - 1) / kPairChunk : 0;
+          int nb = 0;
+          if (need > 0) {
+            if (lane == 0) nb = atomicAdd(bv.nchunks, need);
+            nb = __builtin_amdgcn_readlane(nb, 0);
+            if (lane < need && nb + lane < bv.chunk_cap) {
+              bv.cfill[nb + lane] = kPairChunk;  // the last one is corrected at the end
+              const int at = atomicAdd(&bv.bcnt[B], 1);
+              bv.bchunks[B * bv.maxc + at] = nb + lane;
+            }
+          }
+          int p = incl - cnt;  // this lane's first pair within the wave's append
+  #pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            if ((und >> r) & 1u) {
+              int c, slot;
+              if (p < avail) {
+                c = ccur;
+                slot = cfill_w + p;
+              } else {
+                c = nb + (p - avail) / kPairChunk;
+                slot = (p - avail) % kPairChunk;
+              }
+              if (c < bv.chunk_cap) {
+                const int64_t pos = (int64_t)c * kPairChunk + slot;
+                bv.pair_u[pos] = (int32_t)u;
+                bv.pair_j[pos] = (int32_t)((int64_t)T * TILE + quarter_row(qhalf, half, r));
+                bv.pair_s[pos] = acc[r];
+              } else {
+                ovf |= 1u << r;
+              }
+              ++p;
+            }
+          }
+          if (need > 0) {
+            ccur = nb + need - 1;
+            cfill_w = total - avail - (need - 1) * kPairChunk;
+          } else {
+            cfill_w += total;
           }
         }
-        int p = incl - cnt;  // this lane's first pair within the wave's append
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          if ((und >> r) & 1u) {
-            int c, slot;
-            if (p < avail) {
-              c = ccur;
-              slot = cfill_w + p;
-            } else {
-              c = nb + (p - avail) / kPairChunk;
-              slot = (p - avail) % kPairChunk;
-            }
-            if (c < bv.chunk_cap) {
-              const int64_t pos = (int64_t)c * kPairChunk + slot;
-              bv.pair_u[pos] = (int32_t)u;
-              bv.pair_j[pos] = (int32_t)((int64_t)T * TILE + quarter_row(qhalf, half, r));
-              bv.pair_s[pos] = acc[r];
-            } else {
-              ovf |= 1u << r;
-            }
-            ++p;
+        while (ovf) {  // rare: decide in float64 here
+          const int r = __ffs(ovf) - 1;
+          ovf &= ovf - 1;
+          const int32_t jj = (int32_t)((int64_t)T * TILE + quarter_row(qhalf, half, r));
+          if (decide_f64(ix, bv, u, jj)) {
+            const int32_t jo = bv.perm[jj];
+            atomicOr(&bv.bits[(int64_t)jo * bv.W + (orig_u >> 5)], 1u << (orig_u & 31));
+            atomicAdd(&bv.counts[jo], 1ull);
           }
-        }
-        if (need > 0) {
-          ccur = nb + need - 1;
-          cfill_w = total - avail - (need - 1) * kPairChunk;
-        } else {
-          cfill_w += total;
+          // this path's loads are all complete here: without the explicit
+          // wait the compiler's analysis keeps them pending around the tile
+          // loop and waits for every load before the next tile's products,
+          // the prefetched tile's included
+          __builtin_amdgcn_s_waitcnt(0);
         }
       }
-      while (ovf) {  // rare: decide in float64 here
-        const int r = __ffs(ovf) - 1;
-        ovf &= ovf - 1;
-        const int32_t jj = (int32_t)((int64_t)T * TILE + quarter_row(qhalf, half, r));
-        if (decide_f64(ix, bv, u, jj)) {
-          const int32_t jo = bv.perm[jj];
-          atomicOr(&bv.bits[(int64_t)jo * bv.W + (orig_u >> 5)], 1u << (orig_u & 31));
-          atomicAdd(&bv.counts[jo], 1ull);
-        }
-        // this path's loads are all complete here: without the explicit
-        // wait the compiler's analysis keeps them pending around the tile
-        // loop and waits for every load before the next tile's products,
-        // the prefetched tile's included
-        __builtin_amdgcn_s_waitcnt(0);
-      }
-    }
+    }  // exact tests
 
     }  // hmask
 
@@ -1726,13 +1793,14 @@ void launch_bprep(const DevIndex& ix, const BatchView& bv, const int32_t* ks_dev
   hipLaunchKernelGGL(k_btile, dim3((bv.nq_pad + 3) / 4), blk, 0, s, bv.qs, ks_dev, bv.qn,
                      bv.perm, nq, bv.nq_pad, ix.d, ix.d16, ix.m, bv.qt, ix.bf16 ? bv.qb : nullptr,
                      bv.qn_s, bv.k_s, bv.kofs_s, bv.all);
+  hipLaunchKernelGGL(k_btsum, dim3(bv.nq_pad / TILE), dim3(64), 0, s, bv.qn_s, bv.kofs_s, bv.tsum);
 }
 
 size_t bfilter_lds_bytes(const DevIndex& ix) {
   const size_t tile = ix.bf16 ? (size_t)(ix.d16 / 8) * TILE * 16 : (size_t)(ix.d + (ix.d & 1)) * TILE * 4;
   const bool ldsd = ix.bf16 && (tile / 16 + 255) / 256 <= 2;  // the kernel's direct-load case (NV <= 2)
   const size_t nsb = TILE / ix.bsize;
-  return (ldsd ? 3 : 2) * ((tile + 15) / 16 * 16) + 4 * TILE * 4 +
+  return (ldsd ? 3 : 2) * ((tile + 15) / 16 * 16) + 4 * TILE * 4 + 2 * 8 * 4 +
          (nsb > 1 ? nsb + 1 : 1) * (kBatchChunkMax / TILE) * 8 + 2 * (size_t)ix.kmax * TILE * 4 +
          (size_t)ix.kmax * 4 * (nsb + 1);
 }

@@ -120,7 +120,7 @@ inline BatchSizes batch_sizes(const BatchShape& x, int32_t chunk) {
   }
   z.pc = pc;
   const int64_t d2 = x.d + (x.d & 1);
-  int64_t b = chunk * 4 * 2 + cp * d2 * 4 + (x.bf16 ? cp * x.d16 * 2 : 0) + cp * 12 +
+  int64_t b = chunk * 4 * 2 + cp * d2 * 4 + (x.bf16 ? cp * x.d16 * 2 : 0) + cp * 12 + cp / TILE * 32 +
               chunk * W * 4 + chunk * 8 + chunk + 8 + pc * 12 + chunk * 4;
   if (!x.exact)
     b += std::max<int64_t>(pc, 1) * 4 + std::max<int64_t>(z.chunk_cap, 1) * 4 + 4 +
@@ -149,7 +149,7 @@ inline int32_t batch_chunk(const BatchShape& x, int64_t nq) {
 // beyond them are decided in float64 by the filter).
 struct ScratchLayout {
   size_t bits = 0, counts = 0, qn = 0, perm = 0, qt = 0, qb = 0, qn_s = 0, k_s = 0, kofs_s = 0,
-         all = 0, npairs = 0, ks = 0, pair_u = 0, pair_j = 0, pair_s = 0;
+         tsum = 0, all = 0, npairs = 0, ks = 0, pair_u = 0, pair_j = 0, pair_s = 0;
   size_t fixed = 0;  // bytes before the pair slots
   size_t end = 0;    // bytes of the whole layout
   int64_t pc = 0;    // pair slots
@@ -173,6 +173,7 @@ inline ScratchLayout scratch_layout(const BatchShape& x, int32_t chunk, size_t b
   take(L.qn_s, cp, 4);
   take(L.k_s, cp, 4);
   take(L.kofs_s, cp, 4);
+  take(L.tsum, cp / TILE * 8, 4);
   take(L.all, chunk, 1);
   take(L.npairs, 1, 8);
   take(L.ks, chunk, 4);

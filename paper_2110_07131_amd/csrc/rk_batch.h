@@ -14,6 +14,8 @@ struct BatchView {
   float* qn_s;                  // [nq_pad] sorted norms
   int32_t* k_s;                 // [nq_pad] sorted k (0 = padding or no work)
   int32_t* kofs_s;              // [nq_pad] 64 (max(k,1) - 1): the k's row of the filter's (k, user) tables
+  int32_t* tsum;                // [nq_pad / 64][2][4] per tile and query half: largest norm (bits),
+                                // smallest and largest k row, first row of the largest k (-1: > 2 k's)
   int32_t nq_pad;
   uint32_t* bits;               // [nq][W] result bits by original user id
   int64_t W;                    // words per bitmap row

@@ -50,7 +50,7 @@ struct BatchWS {
   float *qn = nullptr, *qt = nullptr, *qn_s = nullptr, *pair_s = nullptr;
   uint16_t* qb = nullptr;
   unsigned long long* npairs = nullptr;
-  int32_t *perm = nullptr, *k_s = nullptr, *kofs_s = nullptr, *pair_u = nullptr,
+  int32_t *perm = nullptr, *k_s = nullptr, *kofs_s = nullptr, *tsum = nullptr, *pair_u = nullptr,
           *pair_j = nullptr, *ks_dev = nullptr;
   // bounded table: chunked pair slots, per-block chunk lists
   int32_t *pair_st = nullptr, *cfill = nullptr, *nchunks = nullptr, *bcnt = nullptr,
@@ -536,6 +536,7 @@ rk_status ensure_batch_ws(rk_index* h, BatchWS& b, int32_t chunk, hipStream_t s)
   HIPTRY(b.alloc(&b.qn_s, cp));
   HIPTRY(b.alloc(&b.k_s, cp));
   HIPTRY(b.alloc(&b.kofs_s, cp));
+  HIPTRY(b.alloc(&b.tsum, cp / TILE * 8));
   HIPTRY(b.alloc(&b.bits, (size_t)chunk * std::max<int64_t>(W, 1)));
   HIPTRY(b.alloc(&b.counts, chunk));
   HIPTRY(b.alloc(&b.all, chunk));
@@ -638,7 +639,8 @@ rk_status batch_enqueue(rk_index* h, BatchWS& b, const float* qs_dev, int64_t nq
     BatchView bv{};
     bv.qs = qs_dev + c0 * ix.d;
     bv.qn = b.qn; bv.perm = b.perm; bv.qt = b.qt; bv.qb = b.qb;
-    bv.qn_s = b.qn_s; bv.k_s = b.k_s; bv.kofs_s = b.kofs_s; bv.nq_pad = (int32_t)round_up(nc, TILE);
+    bv.qn_s = b.qn_s; bv.k_s = b.k_s; bv.kofs_s = b.kofs_s; bv.tsum = b.tsum;
+    bv.nq_pad = (int32_t)round_up(nc, TILE);
     bv.bits = b.bits; bv.W = W; bv.counts = b.counts; bv.all = b.all; bv.n = ix.n;
     bv.npairs = b.npairs; bv.pair_cap = (int32_t)b.pair_cap;
     bv.pair_u = b.pair_u; bv.pair_j = b.pair_j; bv.pair_s = b.pair_s;
@@ -707,6 +709,7 @@ void carve_ws(const rk_index* h, BatchWS& b, int32_t chunk, unsigned char* base,
   b.qn_s = (float*)(base + L.qn_s);
   b.k_s = (int32_t*)(base + L.k_s);
   b.kofs_s = (int32_t*)(base + L.kofs_s);
+  b.tsum = (int32_t*)(base + L.tsum);
   b.all = (uint8_t*)(base + L.all);
   b.npairs = (unsigned long long*)(base + L.npairs);
   b.ks_dev = (int32_t*)(base + L.ks);

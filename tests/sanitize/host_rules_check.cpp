@@ -105,7 +105,7 @@ int main() {
               ++layouts;
               CHECK(L.end <= bytes && L.fixed <= L.end && L.pc >= 1);
               const size_t starts[] = {L.bits, L.counts, L.qn, L.perm, L.qt, L.qn_s, L.k_s, L.kofs_s,
-                                       L.all, L.npairs, L.ks, L.pair_u, L.pair_j, L.pair_s};
+                                       L.tsum, L.all, L.npairs, L.ks, L.pair_u, L.pair_j, L.pair_s};
               for (size_t v : starts) CHECK(v % 256 == 0 && v < L.end);
               for (size_t i = 1; i < sizeof(starts) / sizeof(starts[0]); ++i)
                 CHECK(starts[i] > starts[i - 1]);  // in order, so regions cannot overlap
