@@ -61,8 +61,11 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=10_000)
     ap.add_argument("--serve-warmup", type=int, default=1_000)
     ap.add_argument("--serve-batch", type=int, default=1024)
-    ap.add_argument("--serve-slots", type=int, default=2,
+    ap.add_argument("--serve-slots", type=int, default=1,
                     help="launches in flight per catalog (continuous batching)")
+    ap.add_argument("--serve-hw-queues", type=int, default=0,
+                    help="GPU_MAX_HW_QUEUES for the serving run (0: the environment's, HIP's "
+                         "default 4 if unset; at most 32)")
     return ap.parse_args()
 
 
@@ -245,6 +248,10 @@ def serve_main(args):
     rate (every request queued at once), then open-loop Poisson arrivals at
     fixed fractions of it; latency runs from a request's scheduled arrival
     to its ids on the host."""
+    # hardware queues the slots' streams are spread over (streams that share
+    # one run in order); read by HIP at the first HIP call
+    hwq = args.serve_hw_queues or int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4)
+    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, hwq))
     import torch
 
     from paper_2110_07131_amd import datagen
@@ -353,6 +360,7 @@ def serve_main(args):
                                "sigma 0.5, k_max 25; catalog uniform, query item from its P, "
                                "k ~ U{1..25}; Poisson arrivals",
                    "max_batch": args.serve_batch, "slots_per_catalog": args.serve_slots,
+                   "hw_queues": hwq,
                    "lb_items": args.lb_items or "m",
                    "requests_per_load": args.serve_requests, "warmup": args.serve_warmup},
         "saturation_qps": sat_qps, "loads": loads, "catalogs": build,
@@ -548,7 +556,8 @@ def main():
         "counters_per_step": {k: st[k] for k in ("blocks_visited", "blocks_pruned", "users_evaluated",
                                                  "lemma1_no", "lemma2_yes", "table_yes", "survivors",
                                                  "scan_items", "rechecks", "results", "scan_long",
-                                                 "scan_full_f64", "scan_handoff")},
+                                                 "scan_full_f64", "scan_handoff", "scan_quarters",
+                                                 "scan_valu_tiles")},
         "build_ms": st0["build_ms"], "index_bytes": st0["footprint_bytes"],
         "cpu_baseline": cpu,
         "cpu_simpfer": simpfer_cpu,

@@ -122,7 +122,12 @@ typedef struct {
     int64_t scan_full_f64;     /* pairs decided by the full float64 scan */
     int64_t scan_handoff;      /* batched scan: users handed from their block (or
                                   group) to a group pass of users from several blocks */
-    int64_t reserved[5];
+    int64_t scan_quarters;     /* batched scan: 32-user x 32-item MFMA products
+                                  computed (scan_items / (1024 scan_quarters) is
+                                  the share of them that was needed) */
+    int64_t scan_valu_tiles;   /* batched scan: item tiles of at most 8 users
+                                  computed on the vector ALU */
+    int64_t reserved[3];
 } rk_stats;
 
 /* Index fields readable with rk_index_export (sorted = descending norm). */
@@ -271,8 +276,24 @@ const char *rk_last_error(void);
  * of the catalog's index; requests that arrive while that launch is on the
  * device are taken by the next free slot, so their work overlaps on the
  * device with the earlier launch (a small late request can finish before a
- * large earlier batch).  Results come back to the host per request.
- * Catalogs run concurrently.
+ * large earlier batch).  While launches of the catalog are on the device, a
+ * free slot joins in only when the first of them to end is expected to run
+ * at least twice as long again as the queued requests take alone (moving
+ * averages of launch time per batch size), so a launch that ends soon is
+ * waited for rather than slowed down by splitting the device.  Results come
+ * back to the host per request.  Catalogs run concurrently.
+ *
+ * Every slot's stream is one of catalogs x slots streams of the process.
+ * HIP spreads streams over GPU_MAX_HW_QUEUES hardware queues (4 unless the
+ * environment sets it), and the launches of streams that share a queue run
+ * in order: a small catalog's launch then waits behind a large catalog's.
+ * With one slot per catalog and the default 4 queues, three catalogs
+ * (50k, 500k and 2M users) measured p50 0.9-1.3 ms and p99 9-19 ms over
+ * all requests; with 8 queues the small catalog's p50 fell to 0.2 ms but
+ * the large catalog's p99 rose to 12-36 ms, and with two slots per catalog
+ * the catalog whose stream shared a queue with the large catalog's waited
+ * behind its launches (p50 2-12 ms).  GPU_MAX_HW_QUEUES is read at the
+ * process's first HIP call.
  *
  * Admission by device-memory footprint: a catalog is admitted when its
  * index's bytes plus, per slot, the batch workspace and buffers for
@@ -297,9 +318,13 @@ typedef struct {
     int32_t max_wait_us;  /* 0: launch as soon as the device is free;
                              > 0: a batch smaller than max_batch may wait up
                              to this long after its oldest request arrived */
-    int32_t slots;        /* 0 -> 2: launches in flight per catalog (1..16); an
+    int32_t slots;        /* 0 -> 1: launches in flight per catalog (1..16); an
                              index whose batches run one query at a time
-                             (tiles too wide for the batched kernels) gets 1 */
+                             (tiles too wide for the batched kernels) gets 1.
+                             More than one pays where a catalog's launches
+                             run for tens of milliseconds (a late request
+                             overlaps them); with several catalogs their
+                             extra streams share hardware queues (see above) */
     int64_t hbm_budget;   /* 0 -> 90% of the device memory free at creation */
     int64_t max_queue;    /* 0 -> 65536: queued requests per catalog */
     int64_t reserved[5];

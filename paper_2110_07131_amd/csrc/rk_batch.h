@@ -71,6 +71,8 @@ size_t bfilter_lds_bytes(const DevIndex& ix);
 size_t bfilter_max_tile_bytes();
 void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s);
+// Bounded table: the grouped linear scan of the chunk's pairs (scan_kernels.hip).
+void launch_bscan(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 // Dynamic LDS of the grouped linear scan (bounded table).
 size_t bscan_lds_bytes(const DevIndex& ix);
 // whether the scan's workgroup (dynamic and static LDS) fits a CU

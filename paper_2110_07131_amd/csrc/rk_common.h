@@ -127,7 +127,7 @@ struct QueryWS {
 // Counter slots (statistics).
 enum Ctr {
   C_BLOCKS = 0, C_PRUNED, C_USERS, C_L1NO, C_L2YES, C_TYES, C_SURV, C_SCAN,
-  C_RCHK, C_RES, C_LONG, C_F64SCAN, C_HANDOFF, C_NCTR
+  C_RCHK, C_RES, C_LONG, C_F64SCAN, C_HANDOFF, C_SQUART, C_SVALU, C_NCTR
 };
 static_assert(C_NCTR <= 16, "the counter array holds 16 slots");
 

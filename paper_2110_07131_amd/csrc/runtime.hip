@@ -766,7 +766,7 @@ struct ServerCatalog {
   std::deque<ServerReq> queue;
   std::vector<ServerSlot*> slots;
   int32_t running = 0;          // slots with a launch in flight
-  std::vector<double> starts;   // start of each running launch
+  std::vector<std::pair<double, int64_t>> starts;  // start and size of each running launch
   int64_t bytes = 0;            // device bytes charged to the budget
   double est_ms[kSizeBuckets];  // moving average of launch time by batch size (< 0: none yet)
   std::condition_variable cv;   // requests queued, a launch ended, or the server stops
@@ -919,12 +919,14 @@ struct rk_server {
   }
 
   // Thread of one slot of catalog ci.  With no launch of the catalog on the
-  // device it takes the queued requests at once.  While another slot's
-  // launch runs, it joins in only when that launch has already run at least
-  // twice as long as the queued requests are expected to take on their own
-  // (measured launch times by batch size): a request arriving early in a
-  // long launch then finishes long before it, while launches of similar
-  // size do not split the device between them (each would finish later).
+  // device it takes the queued requests at once.  While other slots'
+  // launches run, it joins in only when the first of them to end is
+  // expected to run at least twice as long again as the queued requests
+  // take on their own (measured launch times by batch size; before a
+  // launch of that size has been measured: when it has run twice as long):
+  // a request arriving early in a long launch then finishes long before
+  // it, while a launch that ends soon is waited for rather than slowed down
+  // by splitting the device.
   void loop(int32_t ci, ServerCatalog* cat, ServerSlot* c) {
     (void)hipSetDevice(opts.device);
     std::unique_lock<std::mutex> lk(mu);
@@ -946,12 +948,24 @@ struct rk_server {
       if (cat->running > 0 && !stop) {
         const int64_t want = std::min<int64_t>((int64_t)cat->queue.size(), opts.max_batch);
         const double tb = cat->estimate(want);
-        const double elapsed = ms_since(t0) - *std::min_element(cat->starts.begin(), cat->starts.end());
         if (tb < 0) {                       // no estimate yet: wait for the launch to end
           cat->cv.wait(lk);
           continue;
         }
-        if (elapsed < 2 * tb) {
+        const double now = ms_since(t0);
+        double left = INFINITY, elapsed = 0;
+        bool known = true;
+        for (const auto& r : cat->starts) {
+          const double er = cat->estimate(r.second);
+          known = known && er >= 0;
+          left = std::min(left, er - (now - r.first));
+          elapsed = std::max(elapsed, now - r.first);
+        }
+        if (known && left < 2 * tb) {       // ends soon: wait for it
+          cat->cv.wait(lk);
+          continue;
+        }
+        if (!known && elapsed < 2 * tb) {
           cat->cv.wait_for(lk, std::chrono::duration<double, std::milli>(2 * tb - elapsed));
           continue;
         }
@@ -965,12 +979,12 @@ struct rk_server {
       }
       ++cat->running;
       const double started = ms_since(t0);
-      cat->starts.push_back(started);
+      cat->starts.emplace_back(started, nb);
       lk.unlock();
       run_range(ci, cat, c, batch, 0, nb);
       lk.lock();
       const double took = ms_since(t0) - started;
-      cat->starts.erase(std::find(cat->starts.begin(), cat->starts.end(), started));
+      cat->starts.erase(std::find(cat->starts.begin(), cat->starts.end(), std::make_pair(started, nb)));
       --cat->running;
       double& e = cat->est_ms[size_bucket(nb)];
       e = e < 0 ? took : 0.7 * e + 0.3 * took;
@@ -1259,6 +1273,7 @@ rk_status rk_index_stats(const rk_index* hc, rk_stats* o) {
   o->lemma1_no = c[C_L1NO]; o->lemma2_yes = c[C_L2YES]; o->table_yes = c[C_TYES];
   o->survivors = c[C_SURV]; o->scan_items = c[C_SCAN]; o->rechecks = c[C_RCHK]; o->results = c[C_RES];
   o->scan_long = c[C_LONG]; o->scan_full_f64 = c[C_F64SCAN]; o->scan_handoff = c[C_HANDOFF];
+  o->scan_quarters = c[C_SQUART]; o->scan_valu_tiles = c[C_SVALU];
   return RK_OK;
 }
 
@@ -1305,7 +1320,7 @@ void rk_server_opts_default(rk_server_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
   o->max_batch = 1024;
-  o->slots = 2;
+  o->slots = 1;
   o->max_queue = 1 << 16;
 }
 
@@ -1316,7 +1331,7 @@ rk_status rk_server_create(const rk_server_opts* opts, rk_server** out) {
   rk_server_opts_default(&o);
   if (opts) o = *opts;
   if (o.max_batch == 0) o.max_batch = 1024;
-  if (o.slots == 0) o.slots = 2;
+  if (o.slots == 0) o.slots = 1;
   if (o.max_queue == 0) o.max_queue = 1 << 16;
   if (o.max_batch < 0 || o.max_wait_us < 0 || o.hbm_budget < 0 || o.slots < 0 || o.max_queue < 0)
     return fail(RK_E_INVAL, "max_batch, max_wait_us, slots, max_queue and hbm_budget must be >= 0");

@@ -34,22 +34,51 @@ CSRC = os.path.join(HERE, "csrc")
 
 # The sources a kernel is compiled from (its file and the headers it includes).
 KERNEL_SOURCES = {
-    "k_bfilter": ["batch_kernels.hip", "rk_batch.h", "rk_common.h", "rkmips.h"],
-    "k_bscan": ["batch_kernels.hip", "rk_batch.h", "rk_common.h", "rkmips.h"],
-    "k_filter": ["query_kernels.hip", "rk_kernels.h", "rk_common.h", "rkmips.h"],
+    "k_bfilter": ["batch_kernels.hip", "batch_device.h", "rk_batch.h", "rk_common.h", "host_rules.h",
+                  "rkmips.h"],
+    "k_bscan": ["scan_kernels.hip", "batch_device.h", "rk_batch.h", "rk_common.h", "host_rules.h",
+                "rkmips.h"],
+    "k_filter": ["query_kernels.hip", "rk_kernels.h", "rk_common.h", "host_rules.h", "rkmips.h"],
 }
 
 
+def strip_comments(src: str) -> str:
+    """C/C++ source without its comments and blank-line runs: a change to a
+    comment leaves the compiled kernel, and so its hash, as it was."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":  # string or character literal, copied whole
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    lines = [ln.rstrip() for ln in "".join(out).splitlines()]
+    return "\n".join(ln for ln in lines if ln)
+
+
 def source_hash(kernel: str) -> str:
-    """sha256 over the sources of a kernel (csrc/ and include/)."""
+    """sha256 over the sources of a kernel (csrc/ and include/), comments
+    left out."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kernel]:
         path = os.path.join(CSRC, f)
         if not os.path.exists(path):
             path = os.path.join(os.path.dirname(HERE), "include", f)
         h.update(f.encode())
-        with open(path, "rb") as fh:
-            h.update(fh.read())
+        with open(path, encoding="utf-8") as fh:
+            h.update(strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -65,7 +65,8 @@ class Stats(ctypes.Structure):
                 ("survivors", ctypes.c_int64), ("scan_items", ctypes.c_int64),
                 ("rechecks", ctypes.c_int64), ("results", ctypes.c_int64),
                 ("scan_long", ctypes.c_int64), ("scan_full_f64", ctypes.c_int64),
-                ("scan_handoff", ctypes.c_int64), ("reserved", ctypes.c_int64 * 5)]
+                ("scan_handoff", ctypes.c_int64), ("scan_quarters", ctypes.c_int64),
+                ("scan_valu_tiles", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -337,6 +337,10 @@ def test_grouped_scan_handoff_to_group_passes(prec):
     st = idx.stats()
     check_csr(Q, P, qs, ks, off, ids)
     assert st["scan_handoff"] > 0
+    # every scanned (user, item) product comes from an MFMA quarter (32 x 32)
+    # or a vector-ALU tile (at most 8 users x 64 items)
+    assert st["scan_quarters"] > 0
+    assert st["scan_items"] <= 1024 * st["scan_quarters"] + 512 * st["scan_valu_tiles"]
     idx.free()
 
 

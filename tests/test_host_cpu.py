@@ -84,8 +84,17 @@ def test_traffic_summary_from_counter_files(tmp_path):
 def test_source_hash_is_stable_per_kernel():
     h = profiling.source_hash("k_bfilter")
     assert h == profiling.source_hash("k_bfilter") and len(h) == 16
-    assert profiling.source_hash("k_bscan") == h  # same source files
+    assert profiling.source_hash("k_bscan") != h  # its own source file
     assert profiling.source_hash("k_filter") != h
+
+
+def test_source_hash_ignores_comments_only():
+    a = 'int f(int x) { // twice\n  return 2 * x; /* not */\n}\nconst char* s = "//kept";\n'
+    b = '/* header */\nint f(int x) { // once\n  return 2 * x; /* other */\n\n}\nconst char* s = "//kept";\n'
+    sa = profiling.strip_comments(a)
+    assert sa == profiling.strip_comments(b)
+    assert '"//kept"' in sa and "twice" not in sa and "not" not in sa
+    assert profiling.strip_comments("x = 1; // a") != profiling.strip_comments("x = 2; // a")
 
 
 # --- benchmark roofline arithmetic -------------------------------------------
