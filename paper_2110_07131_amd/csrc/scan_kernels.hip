@@ -31,6 +31,10 @@ namespace rk {
 // to group passes that continue 64 such users from any blocks at once.  The
 // lists and their coverage carry over to the next query chunk of the call.
 constexpr int kShortTiles = 4;
+// pass 1 stages a block's chunk ids and fills (at most 64 x 4096 / 256 + 4
+// each) in the candidate region
+static_assert(2 * (TILE * kBatchChunkMax / kPairChunk + 4) <= TILE * TILE,
+              "the chunk lists of a block fit the candidate region");
 // ALIAS mode: floats of the item-tile region (the tile, or the candidates,
 // their rows and the pair slots, whichever is larger)
 __host__ __device__ constexpr int bscan_tile_region(int d2) {
@@ -211,6 +215,7 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   int* plo_s = pk_s + TILE * kUserPairs;
   int* phi_s = plo_s + TILE * kUserPairs;
   __shared__ float eu[TILE];
+  __shared__ float nu_s[TILE];  // |u| of the block's users (pass 1)
   const int32_t* clist = bv.bchunks + B * bv.maxc;
   // sorted index of the user of column c (c < nusers)
   auto urow = [&](int c) -> int64_t { return GROUP ? (int64_t)glist[B * TILE + c] : B * TILE + c; };
@@ -270,6 +275,30 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
   float eut = 0.f, csut = 0.f, hmin = INFINITY;
   int pk[kUserPairs], cnt[kUserPairs];
   float plo[kUserPairs], ph[kUserPairs];
+  // nlim: the first tile end at which an open slot of the user reaches its
+  // Corollary 1 limit; between such tile ends a slot settles only when the
+  // list changes (its count), so the tile loop tests the slots only then.
+  int nlim = INT_MAX;
+  // first tile end j*64 (< m) with cs|u||p_j*64| <= lo, else the end of the
+  // catalog (mB*64 >= m): the test settle makes there, by bisection over
+  // the non-increasing norms
+  auto limit_pos = [&](float lo) -> int {
+    int a = 1, b = (int)ix.mB;
+    while (a < b) {
+      const int mid = (a + b) >> 1;
+      if (csut * ix.normP[(int64_t)mid * TILE] <= lo) b = mid;
+      else a = mid + 1;
+    }
+    return a * TILE;
+  };
+  // the quad's lanes split the open slots, then agree on the minimum
+  auto update_nlim = [&]() {
+    int l = INT_MAX;
+    for (int p = sub; p < kUserPairs; p += 4)
+      if ((rem >> p) & 1u) l = min(l, limit_pos(plo[p]));
+    l = min(l, quad_xor1(l));
+    nlim = min(l, quad_xor2(l));
+  };
   // settles the slots decided no, or covered to their limit at item pos
   // (npos = |p_pos|)
   auto settle = [&](int pos, float npos) {
@@ -407,13 +436,19 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
         }
       } else if (dense && act) {
         const float th = thr[ul];
+        // most tiles of the long pass have no product above the list minimum
+        float mx = acc[0];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = quarter_row(ih, half, r);
-          if (row < left && acc[r] > th) {
-            const int at = atomicAdd(&ccnt[ul], 1);
-            cand[ul * TILE + at] = acc[r];
-            crow[ul * TILE + at] = (uint8_t)row;
+        for (int r = 1; r < 16; ++r) mx = fmaxf(mx, acc[r]);
+        if (left < TILE || mx > th) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = quarter_row(ih, half, r);
+            if (row < left && acc[r] > th) {
+              const int at = atomicAdd(&ccnt[ul], 1);
+              cand[ul * TILE + at] = acc[r];
+              crow[ul * TILE + at] = (uint8_t)row;
+            }
           }
         }
       }
@@ -451,7 +486,10 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
             gpos = pa;
           }
         }
-        if (was_act && !all_users && rem) settle((int)pos, npos);
+        if (was_act && !all_users && rem && (c > 0 || pos >= nlim)) {
+          settle((int)pos, npos);
+          update_nlim();
+        }
         if (sub == 0) {
           if (c > 0) {
             thr[uo] = gmn;
@@ -547,56 +585,89 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
     hi = s + es;
   };
 
-  // Pass 1: every pair, four chunks at a time (independent loads).
+  // Pass 1: every pair of the block, PG chunks at a time.  The chunk ids and
+  // fills are staged in LDS (the candidate region, free until the long
+  // pass), as are the users' norms; the next group's pairs are loaded while
+  // the current group's query data are gathered and its pairs classified.
   // Classes: 0 no, 1 yes, 2 long (flagged), 3 resolve.
   constexpr int PG = 4;
-  for (int cg = 0; cg < (GROUP ? 0 : nch); cg += PG) {
-    int64_t slot[PG];
-    bool ok[PG];
-#pragma unroll
-    for (int g = 0; g < PG; ++g) {
-      ok[g] = false;
-      slot[g] = 0;
-      if (cg + g < nch) {
-        const int32_t c = clist[cg + g];
-        ok[g] = t < bv.cfill[c];
-        slot[g] = (int64_t)c * kPairChunk + t;
-      }
+  int32_t* cid_s = (int32_t*)cand;     // [maxc] chunk ids of the block
+  int32_t* cfl_s = cid_s + bv.maxc;    // [maxc] their fills
+  if (!GROUP) {
+    for (int i = t; i < nch; i += 256) {
+      const int32_t c = clist[i];
+      cid_s[i] = c;
+      cfl_s[i] = bv.cfill[c];
     }
-    int64_t uu[PG];
-    int32_t jv[PG];
-    float sv[PG];
+    if (t < TILE) nu_s[t] = ix.normQ[B * TILE + t];
+    __syncthreads();
+  }
+  int64_t slot[PG];
+  bool ok[PG];
+  int32_t uv[PG], jv[PG];
+  float sv[PG];
+  auto load_group = [&](int cg) {
 #pragma unroll
     for (int g = 0; g < PG; ++g) {
-      uu[g] = ok[g] ? bv.pair_u[slot[g]] : B * TILE;
+      ok[g] = cg + g < nch && t < cfl_s[cg + g];
+      slot[g] = ok[g] ? (int64_t)cid_s[cg + g] * kPairChunk + t : 0;
+    }
+#pragma unroll
+    for (int g = 0; g < PG; ++g) {
+      uv[g] = ok[g] ? bv.pair_u[slot[g]] : (int32_t)(B * TILE);
       jv[g] = ok[g] ? bv.pair_j[slot[g]] : 0;
       sv[g] = ok[g] ? bv.pair_s[slot[g]] : 0.f;
     }
+  };
+  if (!GROUP && nch > 0) load_group(0);
+  for (int cg = 0; cg < (GROUP ? 0 : nch); cg += PG) {
+    // this group's query data first, then the next group's pairs, so that
+    // waiting for the first leaves the second in flight
     int kv[PG];
-    float nqv[PG], nuv[PG];
+    float nqv[PG];
 #pragma unroll
     for (int g = 0; g < PG; ++g) {
       kv[g] = ok[g] ? bv.k_s[jv[g]] : 1;
       nqv[g] = ok[g] ? bv.qn_s[jv[g]] : 0.f;
-      nuv[g] = ok[g] ? ix.normQ[uu[g]] : 0.f;
     }
+    int64_t slot_c[PG];
+    bool ok_c[PG];
+    int32_t uv_c[PG], jv_c[PG];
+    float sv_c[PG];
 #pragma unroll
     for (int g = 0; g < PG; ++g) {
-      if (!ok[g]) continue;
-      const int64_t u = uu[g];
+      slot_c[g] = slot[g];
+      ok_c[g] = ok[g];
+      uv_c[g] = uv[g];
+      jv_c[g] = jv[g];
+      sv_c[g] = sv[g];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (cg + PG < nch) load_group(cg + PG);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int g = 0; g < PG; ++g) {
+      if (!ok_c[g]) continue;
+      const int64_t u = uv_c[g];
       const int ul = (int)(u - B * TILE);
-      const int32_t jj = jv[g];
+      const int32_t jj = jv_c[g];
       const int k = kv[g];
-      const float nu = nuv[g];
+      const float nu = nu_s[ul];
       const float e = e0 * nu + ix.eps_abs;
       const float kth = topk[ul * K + k - 1];
       int cls;
       float lo = 0.f, hi = 0.f;
       const float eb = ix.eps_rel * (nu * nqv[g]) + ix.eps_abs;  // bulk-precision bound
-      if (kth - e > sv[g] + eb) {
+      if (kth - e > sv_c[g] + eb) {
         cls = 0;
       } else {
-        pair_bounds(slot[g], ul, jj, nu, lo, hi);
+        // f(q,u) in [lo, hi]: float32 bounds (recomputed from the float32
+        // rows in bf16 mode, where the filter's product is a bf16 one)
+        float sf = sv_c[g];
+        if (ix.bf16) sf = dot32_col(bv.qs + (int64_t)bv.perm[jj] * d, ubuf + ul, d);
+        const float es = ix.eps_rel32 * (nu * nqv[g]) + ix.eps_abs;
+        lo = sf - es;
+        hi = sf + es;
         const float csu = ix.cs_inflate * nu;
         if (kth - e > hi) {
           cls = 0;
@@ -613,10 +684,10 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
           atomicMax(&phi_s[at], fkey(__float_as_int(hi)));
         }
       }
-      bv.pair_st[slot[g]] = cls == 2;
+      bv.pair_st[slot_c[g]] = cls == 2;
       if (cls == 2) {
         const int at = atomicAdd(&nflag, 1);
-        if (at < flist_cap) flist[at] = (int32_t)slot[g];
+        if (at < flist_cap) flist[at] = (int32_t)slot_c[g];
         ++c_long;
       }
       bool yes = cls == 1;
@@ -699,6 +770,7 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
         // users whose lists already settle every flagged pair stop here
         const int cv = Cov[uo];
         settle(cv, cv < ix.m ? ix.normP[cv] : 0.f);
+        update_nlim();
       }
       if (sub == 0) open[uo] = rem != 0u;
       const unsigned long long still = __ballot(rem != 0u);
