@@ -485,10 +485,13 @@ def main():
     if not args.no_latency:
         nl = min(args.latency_queries, nq)
         times = []
+        gc.collect()
+        gc.disable()  # the interpreter's collector must not pause inside the timed calls
         for i in range(nl):
             t = time.perf_counter()
             idx.reverse_kmips(qs_np[i], int(ks[i]))
             times.append(time.perf_counter() - t)
+        gc.enable()
         times = np.array(times) * 1e3
         lat = {"p50_ms": float(np.percentile(times, 50)), "p99_ms": float(np.percentile(times, 99)),
                "qps": nl / (times.sum() / 1e3), "queries": nl,

@@ -92,7 +92,14 @@ typedef struct {
     int32_t no_blocks;    /* nonzero: no Lemma 3 filter (every block is
                              evaluated: the paper's "Simpfer without blocks",
                              Section 5.2); results are unchanged */
-    int32_t reserved[3];
+    int32_t verify_tiles; /* 0 = default (2048).  Bounded table, one query:
+                             from this many survivors on, the linear scans
+                             (Algorithm 2) run 64 survivors per workgroup
+                             over shared float32 MFMA item tiles instead of
+                             one wave per survivor; < 0: never.  d > 256
+                             always uses one wave per survivor.  Results
+                             are unchanged (a tuning and test hook) */
+    int32_t reserved[2];
 } rk_build_opts;
 
 /* Counters and sizes of an index.  Query counters accumulate over every

@@ -21,6 +21,7 @@ constexpr int kPairChunk = 256;       // slots per pair chunk (bounded table)
 constexpr int kUserPairs = 8;         // flagged-pair slots per user in the scan's long pass
 constexpr int kExactRun = 64;         // exact table: pair slots a filter wave reserves at a time
 constexpr int32_t kMaxD = 512;
+constexpr int32_t kVerifyTilesMaxD = 256;  // widest rows of the one-query tiled scan (prefetch registers)
 constexpr int32_t kMaxKmax = 128;
 constexpr int64_t kBitmapBudget = 512ll << 20;  // bytes of per-query result bits per chunk
 // Undecided-pair slots per chunk of queries.  Exact table: only the pairs

@@ -6,7 +6,9 @@
 //            tests of Lemmas 1 and 2 (and, with an exact table, the k-th
 //            value itself); ballot/popcount compaction of the undecided users
 //  verify    linear scan of the norm-sorted items for each survivor
-//            (Corollaries 1 and 2), one wavefront per survivor, lane = item
+//            (Corollaries 1 and 2), one wavefront per survivor, lane = item;
+//            with many survivors, 64 survivors per workgroup over shared
+//            MFMA item tiles
 //  recheck   float64 recomputation (oracle order) for users whose decision
 //            the bulk precision cannot certify
 //  finalize  result bits (by original id) -> ascending ids
@@ -15,6 +17,7 @@
 // used only when it holds with the error margin of both sides (rk_common.h,
 // margin()); otherwise the user moves on to the next, always sound, step.
 #include "rk_kernels.h"
+#include "batch_device.h"
 
 namespace rk {
 
@@ -197,6 +200,7 @@ __global__ void __launch_bounds__(256) k_verify(DevIndex ix, const float* __rest
   __shared__ __align__(16) float urow_s[4][BF16 ? 4 : 512];
   float* uw = urow_s[threadIdx.x >> 6];
   const int nsurv = ws.cnt[0];
+  if (nsurv >= ix.verify_tiles) return;  // k_verify_tiles takes them
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   const float nq = *ws.qnorm;
   for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < nsurv; w += nwaves) {
@@ -292,12 +296,214 @@ __global__ void __launch_bounds__(256) k_verify(DevIndex ix, const float* __rest
   }
 }
 
+// The same scan for many survivors at once.  A workgroup takes a chunk of up
+// to 512 survivors and scans the norm-sorted item tiles for all of them in
+// rounds: each round, groups of 64 of the chunk's survivors still scanning
+// keep their rows in LDS and walk the round's item tiles together (64x64
+// float32 MFMA products; wave w: survivors of half w&1, items of half w>>1),
+// so each tile is read once per group instead of once per survivor; after
+// the round the survivors that stopped leave and the rest are regrouped,
+// all at the same item position.  Rounds grow from 4 to 64 tiles.  Each
+// (survivor, item) gets the one-wave scan's certified test (beat if
+// u.p - u.q exceeds both margins, float64 inside them); a survivor stops at
+// its Corollary 1 limit or once k items beat q, tested after each tile as
+// above.  Runs when the filter left at least ix.verify_tiles survivors (the
+// one-wave scan then returns at once).
+constexpr int kVtChunk = 512;    // survivors regrouped within a workgroup
+constexpr int kVtGrid = 1024;    // workgroups of the tiled scan
+constexpr int kVtChunks = 256;   // chunks the survivors are split into (while at most 512 each)
+constexpr int kVtRound0 = 4;     // item tiles of the first round
+constexpr int kVtRoundMax = 64;  // ... and of the longest
+
+template <int NV>
+__global__ void __launch_bounds__(256) k_verify_tiles(DevIndex ix, const float* __restrict__ q,
+                                                      int32_t k, QueryWS ws) {
+  const int nsurv = ws.cnt[0];
+  if (nsurv < ix.verify_tiles) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int half = lane >> 5, col = lane & 31, uh = wave & 1, ih = wave >> 1;
+  const int d = ix.d, d2 = d + (d & 1);
+  float* ubuf = (float*)lds_raw;   // [d2][64] the current group's survivors (columns)
+  float* pbuf = ubuf + d2 * TILE;  // [d2][64] the current item tile
+  // the chunk's survivors: sorted user index, u.q, |u|, its margin, limit,
+  // beats so far, float64 used
+  __shared__ int32_t r_c[kVtChunk], stop_c[kVtChunk], beats_c[kVtChunk], f64_c[kVtChunk];
+  __shared__ float s_c[kVtChunk], nu_c[kVtChunk], euq_c[kVtChunk];
+  __shared__ int32_t act_l[2][kVtChunk];  // survivors still scanning (chunk positions), ping-pong
+  __shared__ int32_t gm[TILE];            // chunk position of each column of the group
+  __shared__ int32_t act_n[2];
+  __shared__ float np_s[TILE];
+  const float nq = *ws.qnorm;
+  // chunks of 64..512 survivors, about one per CU (measured against one per
+  // workgroup of the grid, and 512 always, on 48k- and 480k-survivor queries)
+  const int per = min(kVtChunk / TILE, max(1, (nsurv + TILE * kVtChunks - 1) / (TILE * kVtChunks)));
+  const int CH = per * TILE;
+  const int nchunks = (nsurv + CH - 1) / CH;
+  const int nv = d * (TILE / 4);  // 16-byte vectors of an item tile
+  const int u = uh * 32 + col;    // the lane's column
+  unsigned long long c_scan = 0, c_f64 = 0;
+  u32x4 pf[NV];
+  auto load_tile = [&](int64_t I) {
+    const u32x4* src = (const u32x4*)(ix.Pt + I * d * TILE);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (v * 256 + t < nv) pf[v] = src[v * 256 + t];
+  };
+  for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int cnt = min(CH, nsurv - ch * CH);
+    if (t == 0) act_n[0] = 0;
+    __syncthreads();
+    for (int i = t; i < cnt; i += 256) {
+      const int32_t r = ws.surv_idx[(int64_t)ch * CH + i];
+      const float sv = ws.surv_s[(int64_t)ch * CH + i];
+      const float nu = ix.normQ[r];
+      const float euq = margin(ix, nu, nq);
+      const float sl = sv - euq;  // certified lower end of f(q,u)
+      int64_t lo = 0, hi = ix.m;  // Corollary 1 limit, as in the one-wave scan
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((ix.cs_inflate * nu) * ix.normP[mid] <= sl) hi = mid;
+        else lo = mid + 1;
+      }
+      r_c[i] = r;
+      s_c[i] = sv;
+      nu_c[i] = nu;
+      euq_c[i] = euq;
+      stop_c[i] = (int32_t)lo;
+      beats_c[i] = 0;
+      f64_c[i] = 0;
+      if (lo > 0) act_l[0][atomicAdd(&act_n[0], 1)] = i;
+    }
+    __syncthreads();
+    int64_t P = 0;  // item tile every scanning survivor of the chunk has reached
+    int len = kVtRound0, cur = 0;
+    while (act_n[cur] > 0 && P < ix.mB) {
+      const int na = act_n[cur];
+      const int64_t P1 = min(P + (int64_t)len, ix.mB);
+      for (int g0 = 0; g0 < na; g0 += TILE) {
+        const int ng = min(TILE, na - g0);
+        if (t < TILE) gm[t] = t < ng ? act_l[cur][g0 + t] : -1;
+        __syncthreads();
+        for (int i = t; i < d * TILE; i += 256) {
+          const int c = i & (TILE - 1);
+          ubuf[i] = c < ng ? ix.Qrow[(int64_t)r_c[gm[c]] * d + (i >> 6)] : 0.f;
+        }
+        if (d & 1) {
+          if (t < TILE) ubuf[d * TILE + t] = 0.f;
+          else if (t < 2 * TILE) pbuf[d * TILE + t - TILE] = 0.f;
+        }
+        const int mine = u < ng ? gm[u] : -1;
+        load_tile(P);
+        for (int64_t I = P; I < P1; ++I) {
+          __syncthreads();  // the counts of tile I - 1 are in; pbuf is free
+          // every wave reads the same settled state, so all leave together
+          const int gl = lane < ng ? gm[lane] : -1;
+          if (!__ballot(gl >= 0 && beats_c[gl] < k && I * TILE < stop_c[gl])) break;
+          const bool act = mine >= 0 && beats_c[mine] < k && I * TILE < stop_c[mine];
+          {
+            u32x4* dst = (u32x4*)pbuf;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+              if (v * 256 + t < nv) dst[v * 256 + t] = pf[v];
+          }
+          if (t < TILE) np_s[t] = I * TILE + t < ix.m ? ix.normP[I * TILE + t] : 0.f;
+          if (I + 1 < P1) load_tile(I + 1);
+          __syncthreads();  // pbuf holds tile I
+          if (!__ballot(act)) continue;
+          f32x16 acc = {};
+          const float* pa = pbuf + ih * 32 + col + half * TILE;
+          const float* ua = ubuf + uh * 32 + col + half * TILE;
+          for (int ks = 0; ks < d2 / 2; ++ks)
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[2 * ks * TILE], ua[2 * ks * TILE], acc, 0, 0, 0);
+          if (!act) continue;
+          const int stop = stop_c[mine];
+          const float sv = s_c[mine], nu = nu_c[mine], euq = euq_c[mine];
+          int beats = 0;
+          unsigned unc = 0;  // rows inside the margins
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = quarter_row(ih, half, r);
+            // the float32 product's own margin plus u.q's (bulk precision)
+            const float tol = (ix.eps_rel32 * (nu * np_s[row]) + ix.eps_abs) + euq;
+            const float diff = acc[r] - sv;
+            const bool in = I * TILE + row < stop;
+            beats += in && diff > tol;
+            unc |= (unsigned)(in && !(diff > tol) && !(diff <= -tol)) << r;
+          }
+          if (unc) {  // float64 for these items only
+            const float* urow = ix.Qrow + (int64_t)r_c[mine] * d;
+            const double fq = dot64_rows(q, urow, d);
+            for (; unc; unc &= unc - 1) {
+              const int64_t j = I * TILE + quarter_row(ih, half, __ffs(unc) - 1);
+              beats += dot64_rows(ix.Prow + j * d, urow, d) > fq;
+            }
+            f64_c[mine] = 1;
+          }
+          if (beats) atomicAdd(&beats_c[mine], beats);
+          if (ih == 0 && half == 0) c_scan += (unsigned long long)min((int64_t)TILE, (int64_t)stop - I * TILE);
+        }
+        __syncthreads();  // the group's counts are in; gm and ubuf are free
+      }
+      // the survivors still scanning at P1, regrouped for the next round
+      if (t == 0) act_n[cur ^ 1] = 0;
+      __syncthreads();
+      for (int i = t; i < na; i += 256) {
+        const int c = act_l[cur][i];
+        if (beats_c[c] < k && P1 * TILE < stop_c[c]) act_l[cur ^ 1][atomicAdd(&act_n[cur ^ 1], 1)] = c;
+      }
+      __syncthreads();
+      cur ^= 1;
+      P = P1;
+      len = min(2 * len, kVtRoundMax);
+    }
+    for (int i = t; i < cnt; i += 256) {
+      const bool yes = beats_c[i] < k;
+      const int64_t r = r_c[i];
+      if (yes) set_result(ws, ix, r);
+      trace(ws, ix, r,
+            f64_c[i] ? (yes ? RK_C_RECHECK_YES : RK_C_RECHECK_NO) : (yes ? RK_C_SCAN_YES : RK_C_SCAN_NO),
+            NAN);
+      c_f64 += (unsigned long long)f64_c[i];
+    }
+    __syncthreads();  // the chunk's state is read before the next chunk writes it
+  }
+  if (ws.ctr) {
+    for (int off = 32; off > 0; off >>= 1) {
+      c_scan += __shfl_xor(c_scan, off);
+      c_f64 += __shfl_xor(c_f64, off);
+    }
+    if (lane == 0) {
+      ctr_add(ws, C_SCAN, c_scan);
+      ctr_add(ws, C_RCHK, c_f64);
+    }
+  }
+}
+
+template <int NV>
+static void verify_tiles_nv(const DevIndex& ix, const float* q, int32_t k, const QueryWS& ws,
+                            hipStream_t s) {
+  const size_t lds = 2 * (size_t)(ix.d + (ix.d & 1)) * TILE * sizeof(float);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_verify_tiles<NV>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_verify_tiles<NV>, dim3(kVtGrid), dim3(256), lds, s, ix, q, k, ws);
+}
+
 void launch_verify(const DevIndex& ix, const float* q, int32_t k, const QueryWS& ws,
                    hipStream_t s) {
   if (ix.nB == 0 || ix.exact) return;
   dim3 g(512);
   if (ix.bf16) hipLaunchKernelGGL(k_verify<true>, g, dim3(256), 0, s, ix, q, k, ws);
   else hipLaunchKernelGGL(k_verify<false>, g, dim3(256), 0, s, ix, q, k, ws);
+  // the survivor count is known on the device only: both scans are queued,
+  // and the one not meant for it returns at once
+  if (ix.verify_tiles == INT32_MAX) return;
+  const int per_thread = (ix.d * (TILE / 4) + 255) / 256;  // 16-byte vectors of an item tile
+  if (per_thread <= 2) verify_tiles_nv<2>(ix, q, k, ws, s);
+  else if (per_thread <= 4) verify_tiles_nv<4>(ix, q, k, ws, s);
+  else if (per_thread <= 8) verify_tiles_nv<8>(ix, q, k, ws, s);
+  else verify_tiles_nv<16>(ix, q, k, ws, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -82,6 +82,7 @@ struct DevIndex {
   float cs_inflate;      // 1 + gamma64_d + slack: f(p,u) <= cs_inflate*|u|^*|p|^
   float eps_rel32;       // eps_rel of float32 products (the verification pass)
   int32_t handoff_tiles; // batched scan: hand over only with more tiles than this left
+  int32_t verify_tiles;  // one query: from this many survivors on, the tiled linear scan
 };
 
 // f(x, y) in float64, index order, from two contiguous float32 rows: the

@@ -313,6 +313,8 @@ rk_status build_impl(const float* Q, int64_t n, const float* P, int64_t m, int32
   ix.eps_rel = f32_up(eps);
   ix.eps_rel32 = f32_up(h->eps32);
   ix.handoff_tiles = h->opts.handoff_tiles > 0 ? h->opts.handoff_tiles : 512;
+  ix.verify_tiles = h->opts.verify_tiles < 0 || d > kVerifyTilesMaxD ? INT32_MAX
+                    : h->opts.verify_tiles > 0 ? h->opts.verify_tiles : 2048;
   ix.eps_abs = std::ldexp((double)(d + 2), -124);
   ix.cs_inflate = f32_up(1.0 + gamma_(d, 0x1p-53) + 8 * 0x1p-24);
 

@@ -38,7 +38,8 @@ KERNEL_SOURCES = {
                   "rkmips.h"],
     "k_bscan": ["scan_kernels.hip", "batch_device.h", "rk_batch.h", "rk_common.h", "host_rules.h",
                 "rkmips.h"],
-    "k_filter": ["query_kernels.hip", "rk_kernels.h", "rk_common.h", "host_rules.h", "rkmips.h"],
+    "k_filter": ["query_kernels.hip", "batch_device.h", "rk_batch.h", "rk_kernels.h", "rk_common.h",
+                 "host_rules.h", "rkmips.h"],
 }
 
 

@@ -48,7 +48,7 @@ class BuildOpts(ctypes.Structure):
                 ("margin_rel", ctypes.c_double), ("cand_cap", ctypes.c_int32),
                 ("auto_rebuild", ctypes.c_int32), ("pair_cap", ctypes.c_int32),
                 ("handoff_tiles", ctypes.c_int32), ("no_blocks", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("verify_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -178,7 +178,7 @@ def _check(status: int):
 
 def build_opts(precision="fp32", lb_items=0, device=0, margin_rel=0.0, cand_cap=0,
                auto_rebuild=False, pair_cap=0, handoff_tiles=0, block_size=0,
-               no_blocks=False) -> BuildOpts:
+               no_blocks=False, verify_tiles=0) -> BuildOpts:
     o = BuildOpts()
     lib().rk_build_opts_default(ctypes.byref(o))
     o.precision = {"fp32": RK_FP32, "bf16": RK_BF16}[precision] if isinstance(precision, str) else int(precision)
@@ -191,6 +191,7 @@ def build_opts(precision="fp32", lb_items=0, device=0, margin_rel=0.0, cand_cap=
     o.handoff_tiles = int(handoff_tiles)
     o.block_size = int(block_size)
     o.no_blocks = 1 if no_blocks else 0
+    o.verify_tiles = int(verify_tiles)
     return o
 
 
