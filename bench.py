@@ -330,7 +330,7 @@ def serve_main(args):
     print(f"[serve] closed loop: {n_sat} requests in {span:.1f} ms, {sat_qps:.0f} queries/s",
           file=sys.stderr, flush=True)
     loads = []
-    for frac in (0.25, 0.5, 0.75, 0.9):
+    for frac in (0.02, 0.25, 0.5, 0.75, 0.9):
         lam = frac * sat_qps
         ntot = args.serve_warmup + args.serve_requests
         cat, qs, ks = draw(ntot)

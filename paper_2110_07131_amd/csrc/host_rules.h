@@ -52,6 +52,14 @@ inline double eps_bf16(int d) {
   return r + gamma_(d, 0x1p-53) + 16 * 0x1p-24;
 }
 
+// Largest batch that runs one query at a time when the caller may use the
+// index's one-query workspace: a batched launch costs about the same for 1
+// to ~64 queries (every block's prologue), a one-query launch about a fifth
+// to a sixth of it (measured, exact tables: 50k users / d = 50, 0.06 vs 0.02
+// ms; 500k / d = 100, 0.24 vs 0.06 ms; 1M / d = 100, 0.50 vs 0.12 ms; 2M /
+// d = 200, 2.1 vs 0.38 ms per query).
+inline int64_t small_batch_max(int64_t nB) { return std::max<int64_t>(2, nB / 4096); }
+
 // nullptr when the options are valid, else the reason.
 inline const char* opts_error(const rk_build_opts& o) {
   if (o.precision != RK_FP32 && o.precision != RK_BF16) return "precision must be RK_FP32 or RK_BF16";

@@ -606,20 +606,24 @@ bool batch_one_at_a_time(const DevIndex& ix) {
 }
 
 // Enqueues a batch on stream s with workspace b (per-kernel event timing
-// only when `timed`, for the index's own calls).  chunk > 0: queries per
+// only when `timed`, for the index's own calls).  small_direct: the caller
+// is the index's only user, so a batch of at most small_batch_max(nB)
+// queries may run one query at a time on the index's one-query workspace
+// (faster than the batched kernels' per-block cost for so few queries).  chunk > 0: queries per
 // chunk, for a workspace already laid out for it (no growth); direct_ks: the
 // k values go to the device straight from the caller's memory instead of
 // through the workspace's pinned staging.
 rk_status batch_enqueue(rk_index* h, BatchWS& b, const float* qs_dev, int64_t nq,
                         const int32_t* ks, int64_t* offs, int32_t* ids, int64_t cap,
                         hipStream_t s, bool timed, int32_t chunk_fixed = 0,
-                        bool direct_ks = false) {
+                        bool direct_ks = false, bool small_direct = false) {
   const DevIndex& ix = h->ix;
   launch_set_i64(offs, 0, s);
   HIPTRY(hipGetLastError());
   if (nq == 0) return RK_OK;
-  if (batch_one_at_a_time(ix)) {
-    // too wide for the block-resident batched filter: one query at a time
+  if (batch_one_at_a_time(ix) || (small_direct && nq <= small_batch_max(ix.nB))) {
+    // too wide for the block-resident batched filter, or too few queries to
+    // pay for its per-block cost: one query at a time
     for (int64_t i = 0; i < nq; ++i) {
       rk_status st = enqueue_query(h, qs_dev + i * ix.d, ks[i], ids, cap, offs + i, offs + i + 1,
                                    s, nullptr, nullptr);
@@ -893,8 +897,10 @@ struct rk_server {
     int64_t total = 0;
     hipError_t e = hipMemcpyAsync(c->q_dev, c->q_pin, nq * d * sizeof(float), hipMemcpyHostToDevice, c->stream);
     for (int attempt = 0; attempt < 2 && e == hipSuccess; ++attempt) {
+      // with one slot the catalog's index has no other user: small batches
+      // may take the one-query path
       st = batch_enqueue(cat->idx, c->ws, c->q_dev, nq, ks.data(), c->offs_dev, c->ids_dev, c->ids_cap,
-                         c->stream, false);
+                         c->stream, false, 0, false, cat->slots.size() == 1);
       if (st != RK_OK) break;
       e = hipMemcpyAsync(c->offs_pin, c->offs_dev, (nq + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1130,7 +1136,7 @@ rk_status rk_reverse_kmips_batch_dev(rk_index* h, const float* qs_dev, int64_t n
   if (st != RK_OK) return st;
   HIPTRY(hipSetDevice(h->device));
   hipStream_t s = stream ? (hipStream_t)stream : h->stream;
-  return batch_enqueue(h, h->bw, qs_dev, nq, ks, offsets_dev, ids_dev, cap, s, true);
+  return batch_enqueue(h, h->bw, qs_dev, nq, ks, offsets_dev, ids_dev, cap, s, true, 0, false, true);
 }
 
 rk_status rk_reverse_kmips_batch_dev_noalloc(rk_index* h, const float* qs_dev, int64_t nq,

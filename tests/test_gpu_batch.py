@@ -35,6 +35,32 @@ def test_batch_mixed_k_equals_oracle(lb, prec):
 
 
 @pytest.mark.parametrize("lb,prec", MODES)
+def test_small_batches_run_one_query_at_a_time(lb, prec):
+    # batches of one and two queries take the one-query path (the batched
+    # kernels' per-block cost does not pay for them); three take the
+    # batched kernels: every row equals the oracle's, and the rows of the
+    # same queries agree across the three forms
+    w = datagen.config_workload("parity")
+    rng = np.random.default_rng(9)
+    qs = w.queries[:3]
+    ks = rng.integers(1, 11, 3).astype(np.int32)
+    idx = Index.build(w.Q, w.P, 10, lb_items=lb, precision=prec)
+    idx.set_counting(True)
+    rows = {}
+    for nq in (1, 2, 3):
+        before = idx.stats()["blocks_visited"]
+        off, ids = idx.reverse_kmips_batch(qs[:nq], ks[:nq])
+        check_csr(w.Q, w.P, qs[:nq], ks[:nq], off, ids)
+        # the same Lemma 3 work either way: nq x (number of blocks)
+        assert idx.stats()["blocks_visited"] - before == nq * idx.stats()["n_blocks"]
+        for i in range(nq):
+            rows.setdefault(i, []).append(ids[off[i]:off[i + 1]])
+    for i, r in rows.items():
+        assert all(np.array_equal(r[0], x) for x in r[1:]), i
+    idx.free()
+
+
+@pytest.mark.parametrize("lb,prec", MODES)
 @pytest.mark.parametrize("n,m,d,kmax", [(130, 70, 3, 5), (65, 9, 7, 12), (1, 1, 2, 1), (200, 40, 160, 8)])
 def test_batch_ragged_shapes_and_k_above_m(n, m, d, kmax, lb, prec):
     w = datagen.workload(n, m, d, 0.7, 12, seed=n * 7 + d)
