@@ -310,9 +310,30 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   p += ix.kmax * 4;
   float* Yl = (float*)p;  // [kmax][64] "yes" thresholds per (k, user)
 
-  // block minima, then Lemma 3 for the chunk's queries
+  // user tile, lower-bound rows and block minima of this block
+  if (BF16) {
+    const u32x4* src = (const u32x4*)(ix.Qb + B * (int64_t)G * TILE * 8);
+    u32x4* dst = (u32x4*)ubuf;
+    for (int i = t; i < tile_vecs; i += 256) dst[i] = src[i];
+  } else {
+    const u32x4* src = (const u32x4*)(ix.Qt + B * (int64_t)d * TILE);
+    u32x4* dst = (u32x4*)ubuf;
+    for (int i = t; i < d * TILE / 4; i += 256) dst[i] = src[i];
+    if (d & 1) ((float*)ubuf)[d * TILE + (t & 63)] = 0.f;  // zero pad row
+  }
+  for (int i = t; i < ix.kmax * TILE; i += 256)
+    Ll[i] = ix.L32[(int64_t)(i / TILE) * ix.n_pad + B * TILE + (i % TILE)];
   for (int i = t; i < ix.kmax * nsb; i += 256)
     LBl[i] = ix.LB[(int64_t)(i % ix.kmax) * ix.nSB + B * nsb + i / ix.kmax];
+  // yes threshold of (k, user): exact table -> the float above L (>= theta_k);
+  // bounded table -> Lemma 2's bound cs_inflate |u|^ |p_k|^
+  for (int i = t; i < ix.kmax * TILE; i += 256) {
+    const int kk = i / TILE;
+    const float L = ix.L32[(int64_t)kk * ix.n_pad + B * TILE + (i % TILE)];
+    Yl[i] = ix.exact ? f32_next_up(L)
+                     : (ix.cs_inflate * ix.normQ[B * TILE + (i % TILE)]) *
+                           (kk < ix.m ? ix.normP[kk] : INFINITY);
+  }
   __syncthreads();
 
   // Lemma 3 for every query of the chunk and every block b of the tile:
@@ -345,32 +366,6 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
     }
   }
   __syncthreads();
-
-  if (next_live(walk, 0, nT) < nT) {  // the same in every thread (walk is in LDS)
-    // user tile and lower-bound rows of this block, unless Lemma 3 pruned it
-    // for every query of the chunk (the next barrier precedes their use)
-    if (BF16) {
-      const u32x4* src = (const u32x4*)(ix.Qb + B * (int64_t)G * TILE * 8);
-      u32x4* dst = (u32x4*)ubuf;
-      for (int i = t; i < tile_vecs; i += 256) dst[i] = src[i];
-    } else {
-      const u32x4* src = (const u32x4*)(ix.Qt + B * (int64_t)d * TILE);
-      u32x4* dst = (u32x4*)ubuf;
-      for (int i = t; i < d * TILE / 4; i += 256) dst[i] = src[i];
-      if (d & 1) ((float*)ubuf)[d * TILE + (t & 63)] = 0.f;  // zero pad row
-    }
-    for (int i = t; i < ix.kmax * TILE; i += 256)
-      Ll[i] = ix.L32[(int64_t)(i / TILE) * ix.n_pad + B * TILE + (i % TILE)];
-    // yes threshold of (k, user): exact table -> the float above L (>= theta_k);
-    // bounded table -> Lemma 2's bound cs_inflate |u|^ |p_k|^
-    for (int i = t; i < ix.kmax * TILE; i += 256) {
-      const int kk = i / TILE;
-      const float L = ix.L32[(int64_t)kk * ix.n_pad + B * TILE + (i % TILE)];
-      Yl[i] = ix.exact ? f32_next_up(L)
-                       : (ix.cs_inflate * ix.normQ[B * TILE + (i % TILE)]) *
-                             (kk < ix.m ? ix.normP[kk] : INFINITY);
-    }
-  }
 
   const int64_t u = B * TILE + uh * 32 + col;  // this lane's user
   const bool valid = u < ix.n;
