@@ -138,7 +138,7 @@ def precision():
 @pytest.mark.parametrize("lb,prec", [(0, "fp32"), (0, "bf16"), (50, "fp32")])
 def test_precision_config_full_size(precision, lb, prec):
     # 1,000 query items x k in {1,10,25}; lb = 50 is the paper's P' = 2 k_max:
-    # 3,000 queries in six query chunks, lists carried across them, and the
+    # 3,000 queries in two query chunks, lists carried across them, and the
     # last users of most blocks handed to group passes (1,563 item tiles)
     c, w, ks, smp = precision
     idx = Index.build(w.Q, w.P, c["k_max"], precision=prec, lb_items=lb)
