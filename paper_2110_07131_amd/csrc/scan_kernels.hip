@@ -44,7 +44,7 @@ __host__ __device__ constexpr int bscan_tile_region(int d2) {
 }
 constexpr int kFlagCap = 1024;  // flagged pairs listed in LDS per block
 constexpr int kHandoff = 24;    // at most this many users of a block still scanning: hand them over
-constexpr int kGroupHandoff = 12;  // the same for a group pass (but the last)
+constexpr int kGroupHandoff = 16;  // the same for a group pass (but the last)
 constexpr int kGroupLevels = 2;    // group passes (thresholds and depth measured on 1M users x 100k items)
 // ... and only with more than ix.handoff_tiles item tiles left (512 unless
 // the index options say otherwise: shorter tails cost less where they are
