@@ -321,10 +321,31 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
     for (int i = t; i < d * TILE / 4; i += 256) dst[i] = src[i];
     if (d & 1) ((float*)ubuf)[d * TILE + (t & 63)] = 0.f;  // zero pad row
   }
-  for (int i = t; i < ix.kmax * TILE; i += 256)
-    Ll[i] = ix.L32[(int64_t)(i / TILE) * ix.n_pad + B * TILE + (i % TILE)];
+  // lower bounds L_k(u); after the call's first pass over the item prefix
+  // (bounded table) also each user's k-th largest product over it less the
+  // bound on any product's error, and the block minima of the larger
+  // (Definition 4 and Equation 1 over the longer prefix)
+  const int K = bscan_list_len(ix.kmax);
+  const float e0 = ix.eps_rel32 * ix.normP[0];
+  for (int i = t; i < ix.kmax * TILE; i += 256) {
+    const int kk = i / TILE;
+    const int64_t uu = B * TILE + (i % TILE);
+    float L = ix.L32[(int64_t)kk * ix.n_pad + uu];
+    if (bv.lists)
+      L = fmaxf(L, f32_down((double)bv.gl_v[uu * K + kk] - (double)(e0 * ix.normQ[uu] + ix.eps_abs)));
+    Ll[i] = L;
+  }
   for (int i = t; i < ix.kmax * nsb; i += 256)
     LBl[i] = ix.LB[(int64_t)(i % ix.kmax) * ix.nSB + B * nsb + i / ix.kmax];
+  if (bv.lists) {
+    __syncthreads();
+    for (int i = t; i < ix.kmax * nsb; i += 256) {
+      const int kk = i % ix.kmax, sb = i / ix.kmax;
+      float mn = INFINITY;
+      for (int c = sb * ix.bsize; c < (sb + 1) * ix.bsize; ++c) mn = fminf(mn, Ll[kk * TILE + c]);
+      LBl[i] = fmaxf(LBl[i], mn);
+    }
+  }
   // yes threshold of (k, user): exact table -> the float above L (>= theta_k);
   // bounded table -> Lemma 2's bound cs_inflate |u|^ |p_k|^
   for (int i = t; i < ix.kmax * TILE; i += 256) {

@@ -33,6 +33,10 @@ constexpr int64_t kBitmapBudget = 512ll << 20;  // bytes of per-query result bit
 // 3,000 queries) and 500k x 50k, P' = 100, from four to one (673 -> 183 ms).
 constexpr int64_t kPairBudgetExact = 1ll << 24;
 constexpr int64_t kPairBudget = 1ll << 29;
+// Bounded table: batches of at least this many queries run the scan's first
+// pass (the item prefix of every user) before the filter, whose bounds it
+// tightens; smaller ones leave it to the blocks that have pairs.
+constexpr int64_t kPrescanMin = 256;
 
 // Scan list length per user: k_max + 2 rounded up to a multiple of 4.
 constexpr int bscan_list_len(int kmax) { return (kmax + 2 + 3) / 4 * 4; }

@@ -45,6 +45,9 @@ struct BatchView {
   int32_t* gdone;               // [n_pad] items covered (a multiple of 64); 0 at a call's start
   int32_t carry_in;             // 1: the lists hold the previous chunks' state
   int32_t carry_out;            // 1: later chunks follow (store the lists)
+  int32_t prescan;              // 1: the scan's first pass over the item prefix for every
+                                // user block, before the call's first chunk (no pairs)
+  int32_t lists;                // 1: the filter tightens the lower bounds with the lists
   // Users still scanning when at most a few of their block are, handed to
   // passes that scan them in groups of 64 from several blocks (a group pass
   // hands its own last users to the next): the users of two alternating
@@ -73,6 +76,9 @@ void launch_bfilter(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 void launch_bpairs(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 // Bounded table: the grouped linear scan of the chunk's pairs (scan_kernels.hip).
 void launch_bscan(const DevIndex& ix, const BatchView& bv, hipStream_t s);
+// Bounded table: the scan's first pass (the first kShortTiles item tiles)
+// for every user block, leaving each user's list in gl_v/gl_i/gdone.
+void launch_bprescan(const DevIndex& ix, const BatchView& bv, hipStream_t s);
 // Dynamic LDS of the grouped linear scan (bounded table).
 size_t bscan_lds_bytes(const DevIndex& ix);
 // whether the scan's workgroup (dynamic and static LDS) fits a CU

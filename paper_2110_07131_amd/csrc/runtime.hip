@@ -633,6 +633,10 @@ rk_status batch_enqueue(rk_index* h, BatchWS& b, const float* qs_dev, int64_t nq
   }
   const int64_t W = bitmap_words(ix.n);
   const int32_t chunk = chunk_fixed > 0 ? chunk_fixed : batch_chunk(h, nq);
+  // bounded table, large batches: the scan's first pass for every block
+  // first, so that the filter's Lemma 1 and 3 tests use the tighter bounds
+  // of the longer prefix and leave far fewer pairs
+  const bool prescan = !ix.exact && nq >= kPrescanMin;
   rk_status st = RK_OK;
   if (chunk_fixed <= 0 && (st = ensure_batch_ws(h, b, chunk, s)) != RK_OK) return st;
   for (int64_t c0 = 0; c0 < nq; c0 += chunk) {
@@ -656,9 +660,15 @@ rk_status batch_enqueue(rk_index* h, BatchWS& b, const float* qs_dev, int64_t nq
     bv.sg_count = b.sg_count; bv.sg_users = b.sg_users; bv.sg_block = b.sg_block;
     bv.st_np = b.st_np; bv.st_pk = b.st_pk; bv.st_plo = b.st_plo; bv.st_ph = b.st_ph;
     bv.sg_key = b.sg_key; bv.sg_sorted = b.sg_sorted;
-    bv.carry_in = c0 > 0;
+    bv.carry_in = c0 > 0 || prescan;
     bv.carry_out = c0 + nc < nq;
-    if (c0 == 0 && bv.carry_out) launch_bscan_reset(ix, bv, s);  // the scan state is per call
+    bv.lists = prescan;
+    if (c0 == 0 && prescan) {
+      Timer t(h, s, K_BPAIRS, timed);
+      launch_bprescan(ix, bv, s);  // every user's list over the item prefix, before any pair
+    } else if (c0 == 0 && bv.carry_out) {
+      launch_bscan_reset(ix, bv, s);  // the scan state is per call
+    }
     bv.ctr = h->counting ? h->ctr_dev : nullptr;
     { Timer t(h, s, K_BPREP, timed); launch_bprep(ix, bv, b.ks_dev, nc, s); }
     { Timer t(h, s, K_BFILTER, timed); launch_bfilter(ix, bv, s); }

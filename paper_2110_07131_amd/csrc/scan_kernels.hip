@@ -167,8 +167,9 @@ __global__ void __launch_bounds__(256) k_bscan(DevIndex ix, BatchView bv) {
     if (B * TILE >= cnt) return;
     nusers = (int)min((int64_t)TILE, cnt - B * TILE);
   } else {
-    nch = min(bv.bcnt[B], bv.maxc);
-    if (nch == 0) return;
+    // (the first pass of a call over every block: no pairs yet)
+    nch = bv.prescan ? 0 : min(bv.bcnt[B], bv.maxc);
+    if (nch == 0 && !bv.prescan) return;
   }
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -1028,6 +1029,36 @@ static void bscan_nv(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
     hipLaunchKernelGGL((k_bscan<NV, true, ALIAS>), dim3(ix.nB), dim3(256), lds, s, ix, g);
   }
   hipLaunchKernelGGL(k_bdecide, dim3(ix.nB), dim3(256), 0, s, ix, bv);
+}
+
+void launch_bprescan(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
+  if (ix.nB == 0) return;
+  BatchView p = bv;
+  p.prescan = 1;
+  p.carry_in = 0;
+  p.carry_out = 1;  // store every block's lists
+  const size_t lds = bscan_lds_bytes(ix);
+  const int per_thread = (ix.d * (TILE / 4) + 255) / 256;
+  const bool alias = bscan_alias(ix);
+  auto go = [&](const void* f) {
+    if (lds > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  };
+  if (per_thread <= 2) {
+    go((const void*)k_bscan<2, false, false>);
+    hipLaunchKernelGGL((k_bscan<2, false, false>), dim3(ix.nB), dim3(256), lds, s, ix, p);
+  } else if (per_thread <= 4) {
+    go((const void*)k_bscan<4, false, false>);
+    hipLaunchKernelGGL((k_bscan<4, false, false>), dim3(ix.nB), dim3(256), lds, s, ix, p);
+  } else if (per_thread <= 8) {
+    go((const void*)k_bscan<8, false, true>);
+    hipLaunchKernelGGL((k_bscan<8, false, true>), dim3(ix.nB), dim3(256), lds, s, ix, p);
+  } else if (alias) {
+    go((const void*)k_bscan<16, false, true>);
+    hipLaunchKernelGGL((k_bscan<16, false, true>), dim3(ix.nB), dim3(256), lds, s, ix, p);
+  } else {
+    go((const void*)k_bscan<16, false, false>);
+    hipLaunchKernelGGL((k_bscan<16, false, false>), dim3(ix.nB), dim3(256), lds, s, ix, p);
+  }
 }
 
 void launch_bscan(const DevIndex& ix, const BatchView& bv, hipStream_t s) {
