@@ -268,22 +268,33 @@ def test_grouped_scan_many_flagged_pairs(nq):
     idx.free()
 
 
+def away_case(rng, n_users, n_away, n_rest, n_q, d=8):
+    """Users along +x; the n_away largest items point away from them (never
+    above q, but their norms put every Corollary 1 limit past the first pass
+    over the item prefix), the other n_rest are random, and the queries are
+    drawn from those: the long pass runs for every user."""
+    Q = np.column_stack([1 + 0.2 * rng.random(n_users), 0.3 * rng.standard_normal((n_users, d - 1))])
+    away = np.column_stack([-5 - rng.random(n_away), 0.2 * rng.standard_normal((n_away, d - 1))])
+    rest = rng.standard_normal((n_rest, d))
+    rest *= (1 + 2 * rng.random((n_rest, 1))) / np.linalg.norm(rest, axis=1, keepdims=True)
+    P = np.vstack([away, rest]).astype(np.float32)
+    qs = np.ascontiguousarray(P[rng.integers(n_away, n_away + n_rest, n_q)])
+    ks = rng.integers(1, 9, n_q).astype(np.int32)
+    return Q.astype(np.float32), P, qs, ks
+
+
 def test_grouped_scan_lists_carried_across_chunks():
-    # 4,400 queries (two query chunks) over a catalog far longer than the
-    # short pass: the second chunk starts from the first chunk's per-user
+    # 4,400 queries (two query chunks) on the away-pointing catalog: the long
+    # pass runs, and the second chunk starts from the first chunk's per-user
     # lists and scanned lengths
-    w = datagen.workload(400, 3000, 12, 0.7, 3000, seed=14)
-    rng = np.random.default_rng(14)
-    pick = rng.integers(0, 3000, 4400)
-    qs = np.ascontiguousarray(w.P[pick])
-    ks = rng.integers(1, 9, len(qs)).astype(np.int32)
-    idx = Index.build(w.Q, w.P, 8, lb_items=10)
+    w_Q, w_P, qs, ks = away_case(np.random.default_rng(14), 400, 900, 2100, 4400)
+    idx = Index.build(w_Q, w_P, 8, lb_items=10)
     idx.set_counting(True)
     off, ids = idx.reverse_kmips_batch(qs, ks)
     st = idx.stats()
     assert st["scan_long"] > 0
     for i in list(range(0, 4400, 23)) + [4095, 4096, 4399]:
-        assert np.array_equal(ids[off[i]:off[i + 1]], oracle.brute(w.Q, w.P, qs[i], int(ks[i]))), i
+        assert np.array_equal(ids[off[i]:off[i + 1]], oracle.brute(w_Q, w_P, qs[i], int(ks[i]))), i
     # the same queries one chunk at a time give the same rows
     off2, ids2 = idx.reverse_kmips_batch(qs[4096:], ks[4096:])
     assert np.array_equal(off2, off[4096:] - off[4096])
@@ -325,7 +336,7 @@ def test_grouped_scan_early_exit(prec):
     idx.free()
 
 
-def handoff_case(rng):
+def handoff_case(rng, n_mid=40000):
     # 32 users along +x and 224 along +y, mixed in every block (similar
     # norms); 8 large items along +y (the lower-bound prefix: the y users'
     # pairs end at Lemma 1), 40,000 items of norm about 3 nearly orthogonal
@@ -340,9 +351,9 @@ def handoff_case(rng):
     Q = Q[rng.permutation(nx + ny)]
     top = 0.05 * rng.standard_normal((8, d))
     top[:, 1] += 5
-    mid = rng.standard_normal((40000, d))
+    mid = rng.standard_normal((n_mid, d))
     mid[:, :2] *= 0.02
-    mid *= (2.5 + rng.random((40000, 1))) / np.linalg.norm(mid, axis=1, keepdims=True)
+    mid *= (2.5 + rng.random((n_mid, 1))) / np.linalg.norm(mid, axis=1, keepdims=True)
     small = 0.3 * rng.standard_normal((40, d))
     P = np.vstack([top, mid, small]).astype(np.float32)
     qs = 0.05 * rng.standard_normal((20, d))
@@ -406,17 +417,19 @@ def test_grouped_scan_handoff_on_short_catalogs(prec):
 
 
 def test_grouped_scan_handoff_on_short_catalogs_several_chunks():
-    w = datagen.workload(500, 2500, 12, 0.7, 2500, seed=32)
-    rng = np.random.default_rng(32)
-    pick = rng.integers(0, 2500, 4300)
-    qs = np.ascontiguousarray(w.P[pick])
-    ks = rng.integers(1, 9, len(qs)).astype(np.int32)
-    idx = Index.build(w.Q, w.P, 8, lb_items=10, handoff_tiles=1)
+    # 4,300 queries (two chunks) on the hand-off catalog cut to 2,048 items
+    # (32 tiles), handoff_tiles = 1
+    Q, P, qs0, _ = handoff_case(np.random.default_rng(32), n_mid=2000)
+    rng = np.random.default_rng(33)
+    qs = np.ascontiguousarray(qs0[rng.integers(0, len(qs0), 4300)] +
+                              0.01 * rng.standard_normal((4300, qs0.shape[1])).astype(np.float32))
+    ks = rng.integers(1, 9, 4300).astype(np.int32)
+    idx = Index.build(Q, P, 8, lb_items=8, handoff_tiles=1)
     idx.set_counting(True)
     off, ids = idx.reverse_kmips_batch(qs, ks)
     assert idx.stats()["scan_handoff"] > 0
     for i in list(range(0, 4300, 29)) + [4095, 4096, 4299]:
-        assert np.array_equal(ids[off[i]:off[i + 1]], oracle.brute(w.Q, w.P, qs[i], int(ks[i]))), i
+        assert np.array_equal(ids[off[i]:off[i + 1]], oracle.brute(Q, P, qs[i], int(ks[i]))), i
     idx.free()
 
 
