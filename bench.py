@@ -524,9 +524,21 @@ def main():
             for i in np.linspace(0, nq - 1, 4).astype(int):
                 ref = fi.reverse_kmips(qs_np[i], int(ks[i]))
                 assert np.array_equal(fh[fo[i]:fo[i + 1]], ref), f"{name}: batch/single mismatch at {i}"
+            # one counted step: how many (user, query) pairs the bulk
+            # precision left to float64 (the rest were certified)
+            fi.reset_counters()
+            fi.set_counting(True)
+            fi.reverse_kmips_batch_dev(qs, ks, foff, fids, stream)
+            torch.cuda.synchronize()
+            fst = fi.stats()
+            fi.set_counting(False)
             forms[name] = {"value": nq * args.form_steps / fel, "unit": "queries/s",
                            "ms_per_step": 1e3 * fel / args.form_steps, "steps": args.form_steps,
-                           "precision": prec, "lb_items": lb or m}
+                           "precision": prec, "lb_items": lb or m,
+                           "counters_per_step": {k: int(fst[k]) for k in (
+                               "users_evaluated", "lemma1_no", "table_yes", "rechecks", "survivors",
+                               "scan_items", "results")},
+                           "float64_share_of_evaluated": fst["rechecks"] / max(fst["users_evaluated"], 1)}
             print(f"[bench] form {name}: {forms[name]['ms_per_step']:.3f} ms/step, "
                   f"{forms[name]['value']:.0f} queries/s", file=sys.stderr, flush=True)
             fi.free()
