@@ -75,16 +75,17 @@ KERNEL_NAMES = {"filter": "k_filter", "batch_filter": "k_bfilter", "batch_pairs"
                 "recheck": "k_recheck", "finalize": "k_finalize", "verify": "k_verify"}
 
 
-def dominant_roofline(cls: str, times, st: dict, d: int, precision: str) -> dict:
+def dominant_roofline(cls: str, times, st: dict, d: int, precision: str, passes: int = 1) -> dict:
     """Roofline entry of the dominant kernel class from its event-timed
-    launches and the per-step counters.
+    launches over `passes` steps and the counters of one step.
 
     batch_filter (MFMA): algorithmic flops = 2*d (unpadded) per evaluated
     (user, query) pair, i.e. pairs in blocks Lemma 3 did not prune.
     filter (one query, HBM): bytes = 8 per visited block + 64 users x (row +
     norm + bound) per evaluated block."""
-    ms, launches = times
-    avg_s = ms / 1e3 / max(launches, 1)
+    ms, launches_all = times
+    avg_s = ms / 1e3 / max(launches_all, 1)
+    launches = launches_all // max(passes, 1)  # per step
     if cls == "batch_pairs" and st["scan_items"] > 0:
         # bounded table: the grouped scan's float32 MFMA products, 2*d flops
         # per (user, item) product of the scanned prefixes
@@ -455,16 +456,18 @@ def main():
     torch.cuda.synchronize()
     st = idx.stats()
     idx.set_counting(False)
-    idx.set_timing(8 * nq + 64)
-    step()
+    passes = max(3, min(args.steps, 10))
+    idx.set_timing(passes * (8 * nq + 64))
+    for _ in range(passes):
+        step()
     torch.cuda.synchronize()
     kt = idx.kernel_times()
     idx.set_timing(0)
     dom = max(kt, key=lambda c: kt[c][0])
-    roofline = dominant_roofline(dom, kt[dom], st, d, args.precision)
+    roofline = dominant_roofline(dom, kt[dom], st, d, args.precision, passes)
     table = "exact" if (args.lb_items == 0 or args.lb_items >= m) else f"lb{args.lb_items}"
     roofline["traffic"] = measured_traffic(roofline["kernel"], f"{args.config}/{args.precision}/{table}")
-    kernel_share = {c: {"ms_per_step": v[0], "launches": v[1]} for c, v in kt.items()}
+    kernel_share = {c: {"ms_per_step": v[0] / passes, "launches": v[1] // passes} for c, v in kt.items()}
 
     # Batch latency: every query of a step completes when its step does; the
     # steps again, one at a time, each bracketed by device synchronisations.

@@ -12,6 +12,7 @@
 // Algorithm 2 (bounded-table mode) or the float64 recheck.  Results are
 // per-query bitmaps over original user ids, turned into CSR rows at the end.
 #include "batch_device.h"
+#include <atomic>
 #include <climits>
 
 namespace rk {
@@ -268,7 +269,10 @@ template <bool BF16, int NV>
 __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(DevIndex ix, BatchView bv) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int d = ix.d;
-  const int64_t B = blockIdx.x;
+  // the workgroup's user block, and its part of the chunk's query tiles
+  // [T0, nT) (a catalog with few blocks splits each block's tiles)
+  const int64_t B = blockIdx.x % ix.nB;
+  const int part = (int)(blockIdx.x / ix.nB);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int half = lane >> 5, col = lane & 31;
   const int uh = wave & 1, qhalf = wave >> 1;
@@ -276,7 +280,8 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   const int d2 = d + (d & 1);  // fp32 tiles carry an even number of rows
   const int tile_bytes = BF16 ? G * TILE * 16 : d2 * TILE * 4;
   const int tile_vecs = tile_bytes / 16;
-  const int nT = bv.nq_pad / TILE;
+  const int T0 = (int)((int64_t)part * (bv.nq_pad / TILE) / bv.qsplit);
+  const int nT = (int)((int64_t)(part + 1) * (bv.nq_pad / TILE) / bv.qsplit);
   unsigned char* p = lds_raw;
   unsigned char* ubuf = p;
   p += (tile_bytes + 15) / 16 * 16;
@@ -363,27 +368,27 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   for (int sb = 0; sb < nsb; ++sb) {
     const float csb = ix.cs_inflate * ix.bnorm[B * nsb + sb];
     const float* lbs = LBl + sb * ix.kmax;
-    for (int base = 0; base < bv.nq_pad; base += 256) {
+    for (int base = T0 * TILE; base < nT * TILE; base += 256) {
       const int j = base + t;
       int kq = 0;
       float nqq = 0.f;
-      if (j < bv.nq_pad) {
+      if (j < nT * TILE) {
         kq = bv.k_s[j];
         nqq = bv.qn_s[j];
       }
       const bool live = kq > 0 && !(ix.use_blocks && csb * nqq < lbs[kq > 0 ? kq - 1 : 0]);
       const unsigned long long m = __ballot(live);
-      if (lane == 0 && base + wave * TILE < bv.nq_pad) masks[sb * MT + (base + wave * TILE) / TILE] = m;
+      if (lane == 0 && base + wave * TILE < nT * TILE) masks[sb * MT + (base + wave * TILE) / TILE] = m;
       c_vis += kq > 0;
       c_pr += kq > 0 && !live;
     }
   }
   if (nsb > 1) {
     __syncthreads();
-    for (int T0 = t; T0 < bv.nq_pad / TILE; T0 += 256) {
+    for (int Tw = T0 + t; Tw < nT; Tw += 256) {
       unsigned long long u = 0ull;
-      for (int sb = 0; sb < nsb; ++sb) u |= masks[sb * MT + T0];
-      walk[T0] = u;
+      for (int sb = 0; sb < nsb; ++sb) u |= masks[sb * MT + Tw];
+      walk[Tw] = u;
     }
   }
   __syncthreads();
@@ -407,7 +412,7 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   int64_t erun0 = 0;
   int erun = 0, efill = 0;
 
-  int T = next_live(walk, 0, nT), slot = 0;
+  int T = next_live(walk, T0, nT), slot = 0;
   int Tn = next_live(walk, T + 1, nT);
   if constexpr (LDSD) {
     if (T < nT) issue_tile(qsrc, bv, T, tile_bytes, lane, wave, qbuf2[0], meta_n2, meta_k2);
@@ -438,22 +443,68 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
     const uint32_t hmask = (uint32_t)(mask >> (qhalf * 32));
     if (hmask != 0u) {
     // ---- scores of the quarter: S[query][user], 32 x 32, one accumulator
-    // (a second one alternating over the k-steps measured 1-4% slower)
-    f32x16 acc = {};
+    // (a second one alternating over the k-steps measured 1-4% slower).  The
+    // first product takes a zero accumulator operand, which clears none.
+    const f32x16 zero = {};
+    f32x16 acc;
     if (!BF16) {
       const float* qf = (const float*)qbuf + qhalf * 32 + col + half * TILE;
       const float* uf = (const float*)ubuf + uh * 32 + col + half * TILE;
       const int nsteps = d2 / 2;
-      int ks = 0;
-      for (; ks + 4 <= nsteps; ks += 4) {
-        float a[4], b[4];
+      int ks = 1;
+      if constexpr (NV >= 8) {
+        // d > 64 (more than 32 steps): the operands of the next four steps
+        // are read before the current four multiply, so that the reads'
+        // latency hides behind the products.  The read of the group after
+        // the last full one is clamped to that group (read twice, used once),
+        // which keeps every read inside the tile and the code free of
+        // branches between the reads and their products.
+        const int last = nsteps - 4;  // first step of the last full group
+        float a0[4], b0[4], a1[4], b1[4];
+        const float x0 = qf[0], y0 = uf[0];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          a[i] = qf[(2 * (ks + i)) * TILE];
-          b[i] = uf[(2 * (ks + i)) * TILE];
+          a0[i] = qf[(2 * (1 + i)) * TILE];
+          b0[i] = uf[(2 * (1 + i)) * TILE];
         }
+        __builtin_amdgcn_sched_barrier(0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0, y0, zero, 0, 0, 0);
+        for (;;) {
+          int kn = min(ks + 4, last);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[i], acc, 0, 0, 0);
+          for (int i = 0; i < 4; ++i) {
+            a1[i] = qf[(2 * (kn + i)) * TILE];
+            b1[i] = uf[(2 * (kn + i)) * TILE];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[i], b0[i], acc, 0, 0, 0);
+          ks += 4;
+          if (ks > last) break;
+          kn = min(ks + 4, last);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            a0[i] = qf[(2 * (kn + i)) * TILE];
+            b0[i] = uf[(2 * (kn + i)) * TILE];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[i], b1[i], acc, 0, 0, 0);
+          ks += 4;
+          if (ks > last) break;
+        }
+      } else {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(qf[0], uf[0], zero, 0, 0, 0);
+        for (; ks + 4 <= nsteps; ks += 4) {
+          float a[4], b[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            a[i] = qf[(2 * (ks + i)) * TILE];
+            b[i] = uf[(2 * (ks + i)) * TILE];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[i], acc, 0, 0, 0);
+        }
       }
       for (; ks < nsteps; ++ks)
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(qf[2 * ks * TILE], uf[2 * ks * TILE], acc, 0, 0, 0);
@@ -461,7 +512,8 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
       const bf16x8* qv = (const bf16x8*)qbuf + qhalf * 32 + col + half * TILE;
       const bf16x8* uv = (const bf16x8*)ubuf + uh * 32 + col + half * TILE;
       const int nsteps = G / 2;
-      int ks = 0;
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qv[0], uv[0], zero, 0, 0, 0);
+      int ks = 1;
       for (; ks + 2 <= nsteps; ks += 2) {
         const bf16x8 a0 = qv[2 * ks * TILE], b0 = uv[2 * ks * TILE];
         const bf16x8 a1 = qv[(2 * ks + 2) * TILE], b1 = uv[(2 * ks + 2) * TILE];
@@ -489,10 +541,11 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
       const float e = fmaf(a_u, __int_as_float(sm.x), ix.eps_abs);
       const float Lhi = Ll[sm.z + uc];
       if (sm.w == 0) {
-        bool fl = false;
+        // rounding is monotone, so every acc[r] + e < Lhi iff the largest does
+        float mx = acc[0];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) fl |= !(acc[r] + e < Lhi);
-        flag = fl;
+        for (int r = 1; r < 16; ++r) mx = fmaxf(mx, acc[r]);
+        flag = !(mx + e < Lhi);
       } else if (sm.w > 0) {
         const float Llo = Ll[sm.y + uc];
         bool fl = false;
@@ -909,12 +962,37 @@ size_t bfilter_lds_bytes(const DevIndex& ix) {
 // Largest query tile the filter's prefetch registers hold.
 size_t bfilter_max_tile_bytes() { return (size_t)PF_VEC * 256 * 16; }
 
+// Workgroup slots of the device for a kernel and its dynamic LDS (resident
+// workgroups per CU x CUs), cached per device for the last LDS size asked;
+// 0 if the runtime cannot tell.
+constexpr int kSlotDevices = 64;
+static int64_t device_slots(const void* f, size_t lds, std::atomic<uint64_t>* cache) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kSlotDevices) return 0;
+  const uint64_t key = (uint64_t)lds << 24;
+  const uint64_t c = cache[dev].load(std::memory_order_relaxed);
+  if (c != 0 && (c & ~0xFFFFFFull) == key) return (int64_t)(c & 0xFFFFFFull);
+  int occ = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, 256, lds) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const int64_t slots = std::min<int64_t>((int64_t)occ * cus, 0xFFFFFF);
+  cache[dev].store(key | (uint64_t)slots, std::memory_order_relaxed);
+  return slots;
+}
+
 template <bool BF16, int NV>
-static void bfilter_nv(const DevIndex& ix, const BatchView& bv, size_t lds, hipStream_t s) {
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_bfilter<BF16, NV>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_bfilter<BF16, NV>), dim3(ix.nB), dim3(256), lds, s, ix, bv);
+static void bfilter_nv(const DevIndex& ix, const BatchView& bv0, size_t lds, hipStream_t s) {
+  static std::atomic<uint64_t> slots_cache[kSlotDevices];
+  const void* f = (const void*)k_bfilter<BF16, NV>;
+  if (lds > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  BatchView bv = bv0;
+  // exact table: split the query tiles of a catalog with few blocks (the
+  // bounded table keeps one workgroup per block: its pair chunks are listed
+  // per block by the block's own waves)
+  bv.qsplit = ix.exact ? bfilter_qsplit(ix.nB, bv.nq_pad / TILE, device_slots(f, lds, slots_cache)) : 1;
+  hipLaunchKernelGGL((k_bfilter<BF16, NV>), dim3((unsigned)(ix.nB * bv.qsplit)), dim3(256), lds, s, ix,
+                     bv);
 }
 
 template <bool BF16>

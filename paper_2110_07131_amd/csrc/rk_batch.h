@@ -17,6 +17,8 @@ struct BatchView {
   int32_t* tsum;                // [nq_pad / 64][2][4] per tile and query half: largest norm (bits),
                                 // smallest and largest k row, first row of the largest k (-1: > 2 k's)
   int32_t nq_pad;
+  int32_t qsplit;               // filter: query-tile parts per user block (one workgroup each;
+                                // set by launch_bfilter)
   uint32_t* bits;               // [nq][W] result bits by original user id
   int64_t W;                    // words per bitmap row
   unsigned long long* counts;   // [nq] result sizes, caller order

@@ -64,6 +64,24 @@ int main() {
     if (d > 1) CHECK(eps_fp32(d) > eps_fp32(d - 1));
   }
 
+  // query-tile parts of the batched filter: none for catalogs with at
+  // least as many blocks as slots; about two workgroups per slot otherwise,
+  // at most kQSplitMax parts of at least four tiles
+  CHECK(bfilter_qsplit(1563, 63, 0) == 1);
+  CHECK(bfilter_qsplit(1563, 63, 1024) == 1);
+  CHECK(bfilter_qsplit(782, 64, 1024) == 3);
+  CHECK(bfilter_qsplit(782, 8, 1024) == 2);
+  CHECK(bfilter_qsplit(782, 7, 1024) == 1);
+  CHECK(bfilter_qsplit(32, 64, 1024) == kQSplitMax);
+  for (int64_t nb : {1, 2, 100, 1000, 1563, 5000, 8191, 100000})
+    for (int64_t nt : {1, 4, 8, 16, 63, 64})
+      for (int64_t sl : {1, 512, 1024, 2048}) {
+        const int q = bfilter_qsplit(nb, nt, sl);
+        CHECK(q >= 1 && q <= kQSplitMax);
+        CHECK(q == 1 || nt / q >= 4);
+        if (nb >= sl) CHECK(q == 1);
+      }
+
   // workspace sizing over a grid of shapes
   const int64_t ns[] = {0, 1, 63, 64, 65, 2000, 100000, 540000, 1000000, 2000000, 7000000,
                         (int64_t)INT32_MAX - 64};

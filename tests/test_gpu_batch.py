@@ -152,6 +152,30 @@ def test_exact_pair_counter_beyond_int32():
     idx.free()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("bs", [64, 16])
+def test_batch_query_tiles_split_over_workgroups(prec, bs):
+    # 5,000 users (79 blocks, far fewer than the device's workgroup slots):
+    # the exact table's filter splits each block's 32 query tiles over 8
+    # workgroups of 4 tiles.  Every query is counted once per block, and
+    # every result set equals the oracle's.
+    rng = np.random.default_rng(123)
+    w = datagen.workload(5000, 3000, 24, 0.6, 2000, seed=77)
+    qs = np.vstack([w.queries, datagen.vectors(45, 24, 0.6, rng)])  # 2,045: a ragged last tile
+    ks = rng.integers(1, 11, len(qs)).astype(np.int32)
+    idx = Index.build(w.Q, w.P, 10, precision=prec, block_size=bs)
+    idx.set_counting(True)
+    off, ids = idx.reverse_kmips_batch(qs, ks)
+    st = idx.stats()
+    assert st["blocks_visited"] == len(ks) * st["n_blocks"]
+    th = oracle.theta(w.Q, w.P, 10)
+    assert off[0] == 0 and np.all(np.diff(off) >= 0)
+    for i in range(len(ks)):
+        want = oracle.theta_query(th, w.Q, qs[i], int(ks[i]))
+        assert np.array_equal(ids[off[i]:off[i + 1]], want), i
+    idx.free()
+
+
 @pytest.mark.parametrize("lb,prec", MODES)
 def test_batch_integer_ties(lb, prec):
     rng = np.random.default_rng(8)
