@@ -134,7 +134,8 @@ typedef struct {
                                   the share of them that was needed) */
     int64_t scan_valu_tiles;   /* batched scan: item tiles of at most 8 users
                                   computed on the vector ALU */
-    int64_t reserved[3];
+    int64_t updates;           /* catalog updates (rk_index_add_items/_users) */
+    int64_t reserved[2];
 } rk_stats;
 
 /* Index fields readable with rk_index_export (sorted = descending norm). */
@@ -263,6 +264,33 @@ rk_status rk_index_export(const rk_index *idx, int32_t field, void *dst,
 /* Rebuild the lower-bound arrays and blocks with a new k_max from the
  * device-resident sorted copies (Section 4.1, k > k_max).  Synchronous. */
 rk_status rk_index_rebuild(rk_index *idx, int32_t k_max);
+
+/* Catalog updates (Section 4.1: the bounds stay valid as the item set grows;
+ * new users need their own rows and new blocks).  Synchronous; the index
+ * must not be in use (no call in flight on it, and not a catalog of a
+ * server: RK_E_INVAL).  Original ids continue the existing ones: new items
+ * get ids m, m+1, ...; new users n, n+1, ....
+ *
+ * rk_index_add_items: P holds m_new items (host, [m_new][d]).  The items are
+ * re-sorted by norm.  An exact table (lb_items = m) takes the new items'
+ * float64 products into every user's k_max largest values and stays exact
+ * (identical to building from scratch on the grown catalog); a bounded
+ * table keeps its rows, which remain lower bounds of the grown catalog's
+ * k-th largest values (the k-th largest over a subset of the items), and
+ * the linear scan of Algorithm 2 covers the new items.
+ *
+ * rk_index_add_users: Q holds n_new users (host, [n_new][d]).  Their lower-
+ * bound rows are computed as in the build (over the same item prefix), the
+ * users re-sorted by norm with the existing ones, and the blocks of
+ * Definition 5 rebuilt over the grown order: the index equals one built
+ * from scratch on the grown user set.
+ *
+ * Errors: RK_E_INVAL (NULL pointer with a positive count, negative count,
+ * non-finite values, a grown size beyond the library's limits, the index
+ * held by a server); RK_E_NOMEM / RK_E_DEVICE leave the index unusable (free
+ * it). */
+rk_status rk_index_add_items(rk_index *idx, const float *P, int64_t m_new);
+rk_status rk_index_add_users(rk_index *idx, const float *Q, int64_t n_new);
 
 /* Device bytes an index with these sizes and options would own. */
 int64_t rk_index_footprint(int64_t n, int64_t m, int32_t d, int32_t k_max,

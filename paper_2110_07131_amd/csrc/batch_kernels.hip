@@ -364,7 +364,7 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
 
   // Lemma 3 for every query of the chunk and every block b of the tile:
   // query j lives iff cs_inflate * |u_first(b)| * |q_j| >= L^k(b).
-  unsigned long long c_vis = 0, c_pr = 0;
+  uint32_t c_vis = 0, c_pr = 0;  // per-lane counts (< 2^16 after the wave sum)
   for (int sb = 0; sb < nsb; ++sb) {
     const float csb = ix.cs_inflate * ix.bnorm[B * nsb + sb];
     const float* lbs = LBl + sb * ix.kmax;
@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
   const bool valid = u < ix.n;
   const float a_u = ix.eps_rel * ix.normQ[u];
   const int32_t orig_u = valid ? ix.permQ[u] : 0;
-  unsigned long long c_users = 0, c_rest = 0, c_yes = 0;
+  uint32_t c_users = 0, c_rest = 0, c_yes = 0;
 
   const unsigned char* qsrc = BF16 ? (const unsigned char*)bv.qb : (const unsigned char*)bv.qt;
   // float32: prefetch registers for the next tile (tile bytes + 512 bytes of metadata)
@@ -772,12 +772,12 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
       c_pr += __shfl_xor(c_pr, off);
     }
     if (lane == 0) {
-      atomicAdd(&bv.ctr[C_BLOCKS], c_vis);
-      atomicAdd(&bv.ctr[C_PRUNED], c_pr);
-      atomicAdd(&bv.ctr[C_USERS], c_users);
-      atomicAdd(&bv.ctr[C_L1NO], c_users - c_rest);
-      atomicAdd(&bv.ctr[ix.exact ? C_TYES : C_L2YES], c_yes);
-      atomicAdd(&bv.ctr[ix.exact ? C_RCHK : C_SURV], c_rest - c_yes);
+      atomicAdd(&bv.ctr[C_BLOCKS], (unsigned long long)c_vis);
+      atomicAdd(&bv.ctr[C_PRUNED], (unsigned long long)c_pr);
+      atomicAdd(&bv.ctr[C_USERS], (unsigned long long)c_users);
+      atomicAdd(&bv.ctr[C_L1NO], (unsigned long long)(c_users - c_rest));
+      atomicAdd(&bv.ctr[ix.exact ? C_TYES : C_L2YES], (unsigned long long)c_yes);
+      atomicAdd(&bv.ctr[ix.exact ? C_RCHK : C_SURV], (unsigned long long)(c_rest - c_yes));
     }
   }
 }

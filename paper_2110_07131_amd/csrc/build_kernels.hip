@@ -8,6 +8,9 @@
 //               the same arrays over a long prefix (up to all of P): an MFMA
 //               pass keeps each user's items that can reach its k_max-th
 //               value, and only those are recomputed in float64
+//  lb_merge / gather_bounds
+//               catalog updates: new items merged into the exact table; the
+//               rows of old and new users gathered into the grown norm order
 //  blocks       block minima L^j(B) (Equation (1)) and first-user norms
 #include "rk_kernels.h"
 
@@ -386,6 +389,86 @@ void launch_lb_overflow(const DevIndex& ix, int64_t S_end, const int32_t* ovf_li
   else if (ix.kmax <= 32) hipLaunchKernelGGL(k_lb_overflow<32>, g, dim3(64), 0, s, ix, S_end, ovf_list, L64, L32);
   else if (ix.kmax <= 64) hipLaunchKernelGGL(k_lb_overflow<64>, g, dim3(64), 0, s, ix, S_end, ovf_list, L64, L32);
   else hipLaunchKernelGGL(k_lb_overflow<128>, g, dim3(64), 0, s, ix, S_end, ovf_list, L64, L32);
+}
+
+// ---------------------------------------------------------------------------
+// Catalog updates.  New items: the exact table's k_max largest values of
+// each user take the new items' float64 products in (the top-k_max multiset
+// over the grown catalog, so the table stays exact and equals a fresh
+// build's).  One lane per sorted user; Pnew holds the m_new new rows.
+template <int K>
+__global__ void __launch_bounds__(64) k_lb_merge(DevIndex ix, const float* __restrict__ Pnew,
+                                                 int64_t m_new, double* __restrict__ L64,
+                                                 float* __restrict__ L32) {
+  const int64_t r = (int64_t)blockIdx.x * TILE + threadIdx.x;
+  if (r >= ix.n) return;
+  double top[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) top[j] = j < ix.kmax ? L64[(int64_t)j * ix.n_pad + r] : -INFINITY;
+  for (int64_t t = 0; t < m_new; ++t) {
+    const double a = dot64_user_row(ix.Qt, r, ix.d, Pnew + t * ix.d);
+    if (a > top[K - 1]) topk_insert<K>(top, a);
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    if (j < ix.kmax) {
+      L64[(int64_t)j * ix.n_pad + r] = top[j];
+      L32[(int64_t)j * ix.n_pad + r] = f32_down(top[j]);
+    }
+  }
+}
+
+template <int K>
+static void lb_merge_k(const DevIndex& ix, const float* Pnew, int64_t m_new, double* L64, float* L32,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_lb_merge<K>, dim3((unsigned)(ix.n_pad / TILE)), dim3(64), 0, s, ix, Pnew, m_new,
+                     L64, L32);
+}
+
+void launch_lb_merge(const DevIndex& ix, const float* Pnew, int64_t m_new, double* L64, float* L32,
+                     hipStream_t s) {
+  if (ix.n_pad == 0 || m_new == 0) return;
+  if (ix.kmax <= 8) lb_merge_k<8>(ix, Pnew, m_new, L64, L32, s);
+  else if (ix.kmax <= 16) lb_merge_k<16>(ix, Pnew, m_new, L64, L32, s);
+  else if (ix.kmax <= 32) lb_merge_k<32>(ix, Pnew, m_new, L64, L32, s);
+  else if (ix.kmax <= 64) lb_merge_k<64>(ix, Pnew, m_new, L64, L32, s);
+  else lb_merge_k<128>(ix, Pnew, m_new, L64, L32, s);
+}
+
+// New users: the lower-bound rows of the grown user set in its norm order,
+// gathered from the old index's rows (src >= 0: old sorted position) and
+// the new users' rows (src < 0: new user -1 - src); padding rows +inf.
+__global__ void k_gather_bounds(int32_t kmax, int64_t n, int64_t n_pad, const int64_t* __restrict__ src,
+                                const double* __restrict__ L64a, const float* __restrict__ L32a,
+                                int64_t na_pad, const double* __restrict__ L64b,
+                                const float* __restrict__ L32b, int64_t nb_pad, double* __restrict__ L64,
+                                float* __restrict__ L32) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_pad) return;
+  const int64_t sr = r < n ? src[r] : 0;
+  for (int j = 0; j < kmax; ++j) {
+    double v = INFINITY;
+    float v32 = INFINITY;
+    if (r < n) {
+      if (sr >= 0) {
+        v = L64a[(int64_t)j * na_pad + sr];
+        v32 = L32a[(int64_t)j * na_pad + sr];
+      } else {
+        v = L64b[(int64_t)j * nb_pad + (-1 - sr)];
+        v32 = L32b[(int64_t)j * nb_pad + (-1 - sr)];
+      }
+    }
+    L64[(int64_t)j * n_pad + r] = v;
+    L32[(int64_t)j * n_pad + r] = v32;
+  }
+}
+
+void launch_gather_bounds(int32_t kmax, int64_t n, int64_t n_pad, const int64_t* src,
+                          const double* L64a, const float* L32a, int64_t na_pad, const double* L64b,
+                          const float* L32b, int64_t nb_pad, double* L64, float* L32, hipStream_t s) {
+  if (n_pad <= 0) return;
+  hipLaunchKernelGGL(k_gather_bounds, dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0, s, kmax, n,
+                     n_pad, src, L64a, L32a, na_pad, L64b, L32b, nb_pad, L64, L32);
 }
 
 // ---------------------------------------------------------------------------

@@ -23,6 +23,14 @@ void launch_lb_refine(const DevIndex& ix, int32_t cap, const int32_t* cand,
 void launch_lb_overflow(const DevIndex& ix, int64_t S_end, const int32_t* ovf_list,
                         int32_t n_ovf, double* L64, float* L32, hipStream_t s);
 void launch_blocks(const DevIndex& ix, float* LB, float* bnorm, hipStream_t s);
+// Catalog updates: m_new new items (rows Pnew) merged into the exact table
+// of every user; the rows of a grown user set gathered from two tables
+// (src[r] >= 0: row of the first, else row -1 - src[r] of the second).
+void launch_lb_merge(const DevIndex& ix, const float* Pnew, int64_t m_new, double* L64, float* L32,
+                     hipStream_t s);
+void launch_gather_bounds(int32_t kmax, int64_t n, int64_t n_pad, const int64_t* src,
+                          const double* L64a, const float* L32a, int64_t na_pad, const double* L64b,
+                          const float* L32b, int64_t nb_pad, double* L64, float* L32, hipStream_t s);
 
 // ---- online query (Algorithms 2 and 3) -----------------------------------
 void launch_filter(const DevIndex& ix, const float* q, int32_t k, const QueryWS& ws,

@@ -141,8 +141,9 @@ struct rk_index {
   BatchWS bw;
   // build statistics
   double build_ms = 0;
-  int64_t cand_total = 0, cand_ovf = 0, rebuilds = 0;
+  int64_t cand_total = 0, cand_ovf = 0, rebuilds = 0, updates = 0;
   std::atomic<int64_t> queries{0};
+  std::atomic<int32_t> served{0};  // servers holding the index as a catalog
 
   ~rk_index() {
     if (device >= 0) (void)hipSetDevice(device);
@@ -174,6 +175,14 @@ struct rk_index {
         return;
       }
   }
+  void hfree(void* p) {
+    for (auto it = hbufs.begin(); it != hbufs.end(); ++it)
+      if (*it == p) {
+        (void)hipHostFree(p);
+        hbufs.erase(it);
+        return;
+      }
+  }
 };
 
 namespace {
@@ -192,23 +201,15 @@ bool host_values_ok(const float* x, int64_t count) { return values_ok(x, count);
 
 // Build the lower-bound arrays and blocks for the index's current k_max from
 // the sorted device copies (Algorithm 1, lower-bound arrays and blocks).
-rk_status build_bounds(rk_index* h) {
-  DevIndex& ix = h->ix;
+// Lower-bound arrays L64/L32 ([k_max][x.n_pad]) of the users of x over the
+// first x.lb_items sorted items (Algorithm 1): x is the index itself, or a
+// view of it whose users are a catalog update's new users.
+rk_status compute_bounds(rk_index* h, const DevIndex& ix, double* L64, float* L32) {
   hipStream_t s = h->stream;
   const int64_t lb = ix.lb_items;
-  HIPTRY(h->dalloc(&h->L64, (size_t)ix.kmax * ix.n_pad));
-  HIPTRY(h->dalloc(&h->L32, (size_t)ix.kmax * ix.n_pad));
-  HIPTRY(h->dalloc(&h->LB, (size_t)ix.kmax * ix.nSB));
-  HIPTRY(h->dalloc(&h->bnorm, (size_t)ix.nSB));
-  ix.L64 = h->L64;
-  ix.L32 = h->L32;
-  ix.LB = h->LB;
-  ix.bnorm = h->bnorm;
-  h->cand_total = 0;
-  h->cand_ovf = 0;
   if (ix.n_pad > 0) {
     if (lb <= kSeedItems) {
-      launch_lb_exact(ix, lb, h->L64, h->L32, nullptr, s);
+      launch_lb_exact(ix, lb, L64, L32, nullptr, s);
       HIPTRY(hipGetLastError());
     } else {
       // Long prefix: exact seed over the first kSeedItems items, one MFMA pass
@@ -229,13 +230,13 @@ rk_status build_bounds(rk_index* h) {
       if (e != hipSuccess) { cleanup(); HIPTRY(e); }
       launch_lb_exact(bx, kSeedItems, nullptr, nullptr, t0, s);
       launch_lb_candidates(bx, lb, t0, cap, cand, ccount, s);
-      launch_lb_refine(bx, cap, cand, ccount, h->L64, h->L32, ovf, novf, s);
+      launch_lb_refine(bx, cap, cand, ccount, L64, L32, ovf, novf, s);
       int32_t n_ovf = 0;
       e = hipGetLastError();
       if (e == hipSuccess) e = hipMemcpyAsync(&n_ovf, novf, sizeof(int32_t), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e == hipSuccess && n_ovf > 0) {
-        launch_lb_overflow(bx, lb, ovf, n_ovf, h->L64, h->L32, s);
+        launch_lb_overflow(bx, lb, ovf, n_ovf, L64, L32, s);
         e = hipGetLastError();
       }
       std::vector<int32_t> cc(ix.n);
@@ -245,12 +246,156 @@ rk_status build_bounds(rk_index* h) {
       cleanup();
       HIPTRY(e);
       for (int32_t c : cc) h->cand_total += std::min(c, cap);
-      h->cand_ovf = n_ovf;
+      h->cand_ovf += n_ovf;
     }
-    launch_blocks(ix, h->LB, h->bnorm, s);
-    HIPTRY(hipGetLastError());
   }
   HIPTRY(hipStreamSynchronize(s));
+  return RK_OK;
+}
+
+// Block minima and first-user norms of the index's current table.
+rk_status build_blocks(rk_index* h) {
+  DevIndex& ix = h->ix;
+  HIPTRY(h->dalloc(&h->LB, (size_t)ix.kmax * ix.nSB));
+  HIPTRY(h->dalloc(&h->bnorm, (size_t)ix.nSB));
+  ix.LB = h->LB;
+  ix.bnorm = h->bnorm;
+  if (ix.n_pad > 0) {
+    launch_blocks(ix, h->LB, h->bnorm, h->stream);
+    HIPTRY(hipGetLastError());
+  }
+  HIPTRY(hipStreamSynchronize(h->stream));
+  return RK_OK;
+}
+
+rk_status build_bounds(rk_index* h) {
+  DevIndex& ix = h->ix;
+  HIPTRY(h->dalloc(&h->L64, (size_t)ix.kmax * ix.n_pad));
+  HIPTRY(h->dalloc(&h->L32, (size_t)ix.kmax * ix.n_pad));
+  ix.L64 = h->L64;
+  ix.L32 = h->L32;
+  h->cand_total = 0;
+  h->cand_ovf = 0;
+  rk_status st = compute_bounds(h, ix, h->L64, h->L32);
+  if (st != RK_OK) return st;
+  return build_blocks(h);
+}
+
+std::vector<int32_t> sort_desc(const std::vector<double>& key) {
+  std::vector<int32_t> perm(key.size());
+  std::iota(perm.begin(), perm.end(), 0);
+  std::sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+    if (key[a] != key[b]) return key[a] > key[b];
+    return a < b;
+  });
+  return perm;
+}
+
+// One side of the index (users or items) from rows in original order on the
+// device: squared norms, the descending norm order (stable by original
+// index) and the sorted copies with upward-rounded norms (Algorithm 1's
+// first step).  Sets the side's sizes and pointers; perm_out receives the
+// order (sorted position -> original index).
+rk_status build_side(rk_index* h, const float* Xd, int64_t rows, bool users,
+                     std::vector<int32_t>* perm_out) {
+  DevIndex& ix = h->ix;
+  hipStream_t s = h->stream;
+  const int32_t d = ix.d;
+  const int64_t pad = round_up(rows, TILE);
+  double*& s2 = users ? h->s2Q : h->s2P;
+  int32_t*& perm = users ? h->permQ : h->permP;
+  float*& Xt = users ? h->Qt : h->Pt;
+  float*& norm = users ? h->normQ : h->normP;
+  float*& Xrow = users ? h->Qrow : h->Prow;
+  uint16_t*& Xb = users ? h->Qb : h->Pb;
+  HIPTRY(h->dalloc(&s2, (size_t)rows));
+  launch_sqnorms(Xd, rows, d, s2, s);
+  HIPTRY(hipGetLastError());
+  std::vector<double> key(rows);
+  if (rows) HIPTRY(hipMemcpyAsync(key.data(), s2, rows * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPTRY(hipStreamSynchronize(s));
+  std::vector<int32_t> pr = sort_desc(key);
+  HIPTRY(h->dalloc(&perm, (size_t)rows));
+  if (rows) HIPTRY(hipMemcpyAsync(perm, pr.data(), rows * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPTRY(h->dalloc(&Xt, (size_t)pad * d));
+  HIPTRY(h->dalloc(&norm, (size_t)pad));
+  HIPTRY(h->dalloc(&Xrow, (size_t)rows * d));
+  if (ix.bf16) HIPTRY(h->dalloc(&Xb, (size_t)pad * ix.d16));
+  launch_tile_rows(Xd, perm, s2, rows, pad, d, ix.d16, Xt, norm, ix.bf16 ? Xb : nullptr, Xrow, s);
+  HIPTRY(hipGetLastError());
+  HIPTRY(hipStreamSynchronize(s));
+  if (users) {
+    ix.n = rows;
+    ix.n_pad = pad;
+    ix.nB = (int32_t)(pad / TILE);
+    ix.nSB = (int32_t)(pad / ix.bsize);
+    ix.Qt = h->Qt; ix.Qrow = h->Qrow; ix.Qb = h->Qb; ix.normQ = h->normQ; ix.permQ = h->permQ;
+  } else {
+    ix.m = rows;
+    ix.m_pad = pad;
+    ix.mB = (int32_t)(pad / TILE);
+    ix.Pt = h->Pt; ix.Pb = h->Pb; ix.Prow = h->Prow; ix.normP = h->normP;
+  }
+  if (perm_out) *perm_out = std::move(pr);
+  return RK_OK;
+}
+
+void free_side(rk_index* h, bool users) {
+  if (users) {
+    for (void* p : {(void*)h->s2Q, (void*)h->permQ, (void*)h->Qt, (void*)h->normQ, (void*)h->Qrow, (void*)h->Qb})
+      if (p) h->dfree(p);
+    h->s2Q = nullptr; h->permQ = nullptr; h->Qt = nullptr; h->normQ = nullptr; h->Qrow = nullptr; h->Qb = nullptr;
+  } else {
+    for (void* p : {(void*)h->s2P, (void*)h->permP, (void*)h->Pt, (void*)h->normP, (void*)h->Prow, (void*)h->Pb})
+      if (p) h->dfree(p);
+    h->s2P = nullptr; h->permP = nullptr; h->Pt = nullptr; h->normP = nullptr; h->Prow = nullptr; h->Pb = nullptr;
+  }
+}
+
+// The one-query workspace and staging sized by the number of users.
+rk_status alloc_user_ws(rk_index* h) {
+  const int64_t n = h->ix.n, W = (n + 31) / 32;
+  hipStream_t s = h->stream;
+  HIPTRY(h->dalloc(&h->ws.rbits, (size_t)std::max<int64_t>(W, 1)));
+  HIPTRY(h->dalloc(&h->ws.surv_idx, (size_t)h->ix.n_pad));
+  HIPTRY(h->dalloc(&h->ws.surv_s, (size_t)h->ix.n_pad));
+  HIPTRY(h->dalloc(&h->ws.rchk_idx, (size_t)h->ix.n_pad));
+  HIPTRY(h->dalloc(&h->ids_dev, (size_t)std::max<int64_t>(n, 1)));
+  HIPTRY(hipMemsetAsync(h->ws.rbits, 0, std::max<int64_t>(W, 1) * sizeof(uint32_t), s));
+  HIPTRY(hipHostMalloc((void**)&h->ids_host, std::max<int64_t>(n, 1) * sizeof(int32_t), hipHostMallocMapped));
+  h->hbufs.push_back(h->ids_host);
+  HIPTRY(hipHostGetDevicePointer((void**)&h->ids_host_dev, h->ids_host, 0));
+  HIPTRY(hipStreamSynchronize(s));
+  return RK_OK;
+}
+
+void free_user_ws(rk_index* h) {
+  for (void* p : {(void*)h->ws.rbits, (void*)h->ws.surv_idx, (void*)h->ws.surv_s, (void*)h->ws.rchk_idx,
+                  (void*)h->ids_dev})
+    if (p) h->dfree(p);
+  if (h->ids_host) h->hfree(h->ids_host);
+  h->ws.rbits = nullptr; h->ws.surv_idx = nullptr; h->ws.surv_s = nullptr; h->ws.rchk_idx = nullptr;
+  h->ids_dev = nullptr; h->ids_host = nullptr; h->ids_host_dev = nullptr;
+}
+
+// Rows of one side in original order, on the host (from the sorted copy and
+// its order).
+rk_status side_rows_host(rk_index* h, bool users, std::vector<float>& out) {
+  const int64_t rows = users ? h->ix.n : h->ix.m;
+  const int32_t d = h->ix.d;
+  std::vector<float> sorted((size_t)rows * d);
+  std::vector<int32_t> perm(rows);
+  hipStream_t s = h->stream;
+  if (rows) {
+    HIPTRY(hipMemcpyAsync(sorted.data(), users ? h->Qrow : h->Prow, (size_t)rows * d * sizeof(float),
+                          hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(perm.data(), users ? h->permQ : h->permP, rows * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+  }
+  HIPTRY(hipStreamSynchronize(s));
+  out.resize((size_t)rows * d);
+  for (int64_t i = 0; i < rows; ++i)
+    std::memcpy(&out[(size_t)perm[i] * d], &sorted[(size_t)i * d], d * sizeof(float));
   return RK_OK;
 }
 
@@ -348,76 +493,31 @@ rk_status build_impl(const float* Q, int64_t n, const float* P, int64_t m, int32
     if (bad) { free_tmp(); return bail(fail(RK_E_INVAL, "input has a non-finite value or |x| >= 2^40")); }
   }
 
-  // Step 1: squared norms, descending norm sort (stable by original index).
-  TTRY(h->dalloc(&h->s2Q, (size_t)n));
-  TTRY(h->dalloc(&h->s2P, (size_t)m));
-  launch_sqnorms(Qd, n, d, h->s2Q, s);
-  launch_sqnorms(Pd, m, d, h->s2P, s);
-  TTRY(hipGetLastError());
-  std::vector<double> k2Q(n), k2P(m);
-  if (n) TTRY(hipMemcpyAsync(k2Q.data(), h->s2Q, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  if (m) TTRY(hipMemcpyAsync(k2P.data(), h->s2P, m * sizeof(double), hipMemcpyDeviceToHost, s));
-  TTRY(hipStreamSynchronize(s));
-  auto sort_desc = [](const std::vector<double>& key) {
-    std::vector<int32_t> perm(key.size());
-    std::iota(perm.begin(), perm.end(), 0);
-    std::sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
-      if (key[a] != key[b]) return key[a] > key[b];
-      return a < b;
-    });
-    return perm;
-  };
-  std::vector<int32_t> pQ = sort_desc(k2Q), pP = sort_desc(k2P);
-  TTRY(h->dalloc(&h->permQ, (size_t)n));
-  TTRY(h->dalloc(&h->permP, (size_t)m));
-  if (n) TTRY(hipMemcpyAsync(h->permQ, pQ.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  if (m) TTRY(hipMemcpyAsync(h->permP, pP.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));
-
-  // Sorted tiled copies and upward-rounded norms.
-  TTRY(h->dalloc(&h->Qt, (size_t)ix.n_pad * d));
-  TTRY(h->dalloc(&h->normQ, (size_t)ix.n_pad));
-  TTRY(h->dalloc(&h->Pt, (size_t)ix.m_pad * d));
-  TTRY(h->dalloc(&h->normP, (size_t)ix.m_pad));
-  TTRY(h->dalloc(&h->Prow, (size_t)m * d));
-  TTRY(h->dalloc(&h->Qrow, (size_t)n * d));
-  if (ix.bf16) {
-    TTRY(h->dalloc(&h->Qb, (size_t)ix.n_pad * ix.d16));
-    TTRY(h->dalloc(&h->Pb, (size_t)ix.m_pad * ix.d16));
+  // Step 1: squared norms, descending norm sort (stable by original index),
+  // sorted tiled copies and upward-rounded norms.
+  if ((st = build_side(h, Qd, n, true, nullptr)) != RK_OK || (st = build_side(h, Pd, m, false, nullptr)) != RK_OK) {
+    free_tmp();
+    return bail(st);
   }
-  launch_tile_rows(Qd, h->permQ, h->s2Q, n, ix.n_pad, d, ix.d16, h->Qt, h->normQ, h->Qb, h->Qrow, s);
-  launch_tile_rows(Pd, h->permP, h->s2P, m, ix.m_pad, d, ix.d16, h->Pt, h->normP, h->Pb, h->Prow, s);
-  TTRY(hipGetLastError());
-  TTRY(hipStreamSynchronize(s));
   free_tmp();
-  ix.Qt = h->Qt; ix.Qrow = h->Qrow; ix.Qb = h->Qb; ix.normQ = h->normQ; ix.permQ = h->permQ;
-  ix.Pt = h->Pt; ix.Pb = h->Pb; ix.Prow = h->Prow; ix.normP = h->normP;
 
   // Steps 2-3: lower-bound arrays and blocks.
   if ((st = build_bounds(h)) != RK_OK) return bail(st);
 
   // Query workspace.
-  const int64_t W = (n + 31) / 32;
-  BTRY(h->dalloc(&h->ws.rbits, (size_t)std::max<int64_t>(W, 1)));
-  BTRY(h->dalloc(&h->ws.surv_idx, (size_t)ix.n_pad));
-  BTRY(h->dalloc(&h->ws.surv_s, (size_t)ix.n_pad));
-  BTRY(h->dalloc(&h->ws.rchk_idx, (size_t)ix.n_pad));
+  if ((st = alloc_user_ws(h)) != RK_OK) return bail(st);
   BTRY(h->dalloc(&h->ws.cnt, 4));
   BTRY(h->dalloc(&h->ws.qnorm, 1));
   BTRY(h->dalloc(&h->ctr_dev, 16));
   BTRY(h->dalloc(&h->q_dev, (size_t)d));
-  BTRY(h->dalloc(&h->ids_dev, (size_t)std::max<int64_t>(n, 1)));
   BTRY(h->dalloc(&h->count_dev, 1));
-  BTRY(hipMemsetAsync(h->ws.rbits, 0, std::max<int64_t>(W, 1) * sizeof(uint32_t), s));
   BTRY(hipMemsetAsync(h->ws.cnt, 0, 4 * sizeof(int32_t), s));
   BTRY(hipMemsetAsync(h->ctr_dev, 0, 16 * sizeof(unsigned long long), s));
   h->ws.ctr = nullptr;
   BTRY(hipHostMalloc((void**)&h->q_host, d * sizeof(float), hipHostMallocDefault));
   h->hbufs.push_back(h->q_host);
-  BTRY(hipHostMalloc((void**)&h->ids_host, std::max<int64_t>(n, 1) * sizeof(int32_t), hipHostMallocMapped));
-  h->hbufs.push_back(h->ids_host);
   BTRY(hipHostMalloc((void**)&h->count_host, sizeof(int64_t), hipHostMallocMapped));
   h->hbufs.push_back(h->count_host);
-  BTRY(hipHostGetDevicePointer((void**)&h->ids_host_dev, h->ids_host, 0));
   BTRY(hipHostGetDevicePointer((void**)&h->count_host_dev, h->count_host, 0));
   BTRY(hipStreamSynchronize(s));
   h->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
@@ -1025,6 +1125,7 @@ struct rk_server {
         free_slot_buffers(c);
         delete c;
       }
+      cat->idx->served--;
       delete cat;
     }
   }
@@ -1061,6 +1162,7 @@ void rk_index_free(rk_index* idx) { delete idx; }
 
 rk_status rk_index_rebuild(rk_index* h, int32_t k_max) {
   if (!h) return fail(RK_E_INVAL, "index is NULL");
+  if (h->served > 0) return fail(RK_E_INVAL, "the index is a catalog of a server (free the server first)");
   if (k_max < 1 || k_max > kMaxKmax) return fail(RK_E_INVAL, "k_max must be in [1, 128]");
   HIPTRY(hipSetDevice(h->device));
   auto t0 = std::chrono::steady_clock::now();
@@ -1070,6 +1172,162 @@ rk_status rk_index_rebuild(rk_index* h, int32_t k_max) {
   rk_status st = build_bounds(h);
   if (st != RK_OK) return st;
   h->rebuilds++;
+  h->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return RK_OK;
+}
+
+rk_status rk_index_add_items(rk_index* h, const float* P, int64_t m_new) {
+  if (!h) return fail(RK_E_INVAL, "index is NULL");
+  if (h->served > 0) return fail(RK_E_INVAL, "the index is a catalog of a server (free the server first)");
+  if (m_new < 0 || (m_new > 0 && !P)) return fail(RK_E_INVAL, "P is NULL or m_new < 0");
+  if (m_new == 0) return RK_OK;
+  DevIndex& ix = h->ix;
+  rk_status st = check_sizes(ix.n, ix.m + m_new, ix.d, ix.kmax);
+  if (st != RK_OK) return st;
+  if (!host_values_ok(P, m_new * ix.d)) return fail(RK_E_INVAL, "input has a non-finite value or |x| >= 2^40");
+  HIPTRY(hipSetDevice(h->device));
+  auto t0 = std::chrono::steady_clock::now();
+  HIPTRY(hipDeviceSynchronize());
+  const int64_t m_old = ix.m, m_all = m_old + m_new;
+  const int32_t d = ix.d;
+  std::vector<float> rows;
+  if ((st = side_rows_host(h, false, rows)) != RK_OK) return st;
+  rows.resize((size_t)m_all * d);
+  std::memcpy(&rows[(size_t)m_old * d], P, (size_t)m_new * d * sizeof(float));
+  float* Pall = nullptr;
+  HIPTRY(hipMalloc(&Pall, (size_t)m_all * d * sizeof(float)));
+  hipError_t e = hipMemcpyAsync(Pall, rows.data(), (size_t)m_all * d * sizeof(float), hipMemcpyHostToDevice,
+                                h->stream);
+  if (e != hipSuccess) { (void)hipFree(Pall); HIPTRY(e); }
+  free_side(h, false);
+  st = build_side(h, Pall, m_all, false, nullptr);
+  if (st == RK_OK && ix.exact) {
+    // the exact table stays exact: each user's k_max largest values take
+    // the new items' products in
+    launch_lb_merge(ix, Pall + m_old * d, m_new, h->L64, h->L32, h->stream);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) { (void)hipFree(Pall); HIPTRY(e); }
+    ix.lb_items = (int32_t)m_all;
+    h->dfree(h->LB);
+    h->dfree(h->bnorm);
+    st = build_blocks(h);
+  }
+  // (a bounded table keeps its rows: the k-th largest value over the first
+  // lb_items items of the old order only grows with more items, so they
+  // stay lower bounds, and the linear scan covers the grown catalog)
+  (void)hipFree(Pall);
+  if (st != RK_OK) return st;
+  h->updates++;
+  h->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return RK_OK;
+}
+
+rk_status rk_index_add_users(rk_index* h, const float* Q, int64_t n_new) {
+  if (!h) return fail(RK_E_INVAL, "index is NULL");
+  if (h->served > 0) return fail(RK_E_INVAL, "the index is a catalog of a server (free the server first)");
+  if (n_new < 0 || (n_new > 0 && !Q)) return fail(RK_E_INVAL, "Q is NULL or n_new < 0");
+  if (n_new == 0) return RK_OK;
+  DevIndex& ix = h->ix;
+  rk_status st = check_sizes(ix.n + n_new, ix.m, ix.d, ix.kmax);
+  if (st != RK_OK) return st;
+  if (!host_values_ok(Q, n_new * ix.d)) return fail(RK_E_INVAL, "input has a non-finite value or |x| >= 2^40");
+  HIPTRY(hipSetDevice(h->device));
+  auto t0 = std::chrono::steady_clock::now();
+  HIPTRY(hipDeviceSynchronize());
+  hipStream_t s = h->stream;
+  const int64_t n_old = ix.n, n_all = n_old + n_new;
+  const int64_t old_pad = ix.n_pad, new_pad = round_up(n_new, TILE);
+  const int32_t d = ix.d, K = ix.kmax;
+  std::vector<void*> tmp;
+  auto cleanup = [&]() { for (void* p : tmp) (void)hipFree(p); tmp.clear(); };
+#define UTRY(expr)                                       \
+  do {                                                   \
+    hipError_t ue_ = (expr);                             \
+    if (ue_ != hipSuccess) { cleanup(); HIPTRY(ue_); }   \
+  } while (0)
+  auto talloc = [&](void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 1));
+    if (e == hipSuccess) tmp.push_back(*p);
+    return e;
+  };
+  // 1. the new users' lower-bound rows, from a view of the index whose users
+  // are the new ones (in their given order)
+  float *Qn = nullptr, *Qtn = nullptr, *normn = nullptr, *rown = nullptr, *L32n = nullptr;
+  double *s2n = nullptr, *L64n = nullptr;
+  int32_t* idn = nullptr;
+  uint16_t* Qbn = nullptr;
+  UTRY(talloc((void**)&Qn, (size_t)n_new * d * sizeof(float)));
+  UTRY(talloc((void**)&s2n, (size_t)n_new * sizeof(double)));
+  UTRY(talloc((void**)&idn, (size_t)n_new * sizeof(int32_t)));
+  UTRY(talloc((void**)&Qtn, (size_t)new_pad * d * sizeof(float)));
+  UTRY(talloc((void**)&normn, (size_t)new_pad * sizeof(float)));
+  UTRY(talloc((void**)&rown, (size_t)n_new * d * sizeof(float)));
+  if (ix.bf16) UTRY(talloc((void**)&Qbn, (size_t)new_pad * ix.d16 * sizeof(uint16_t)));
+  UTRY(talloc((void**)&L64n, (size_t)K * new_pad * sizeof(double)));
+  UTRY(talloc((void**)&L32n, (size_t)K * new_pad * sizeof(float)));
+  std::vector<int32_t> iden(n_new);
+  std::iota(iden.begin(), iden.end(), 0);
+  UTRY(hipMemcpyAsync(Qn, Q, (size_t)n_new * d * sizeof(float), hipMemcpyHostToDevice, s));
+  UTRY(hipMemcpyAsync(idn, iden.data(), n_new * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  launch_sqnorms(Qn, n_new, d, s2n, s);
+  launch_tile_rows(Qn, idn, s2n, n_new, new_pad, d, ix.d16, Qtn, normn, Qbn, rown, s);
+  UTRY(hipGetLastError());
+  DevIndex tx = ix;
+  tx.n = n_new;
+  tx.n_pad = new_pad;
+  tx.nB = (int32_t)(new_pad / TILE);
+  tx.nSB = (int32_t)(new_pad / ix.bsize);
+  tx.Qt = Qtn; tx.normQ = normn; tx.Qb = Qbn; tx.Qrow = rown; tx.permQ = idn;
+  st = compute_bounds(h, tx, L64n, L32n);
+  if (st != RK_OK) { cleanup(); return st; }
+  // 2. the grown user side in its norm order
+  std::vector<float> rows;
+  std::vector<int32_t> perm_old(n_old);
+  if (n_old) UTRY(hipMemcpyAsync(perm_old.data(), h->permQ, n_old * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  if ((st = side_rows_host(h, true, rows)) != RK_OK) { cleanup(); return st; }
+  rows.resize((size_t)n_all * d);
+  std::memcpy(&rows[(size_t)n_old * d], Q, (size_t)n_new * d * sizeof(float));
+  float* Qall = nullptr;
+  UTRY(talloc((void**)&Qall, (size_t)n_all * d * sizeof(float)));
+  UTRY(hipMemcpyAsync(Qall, rows.data(), (size_t)n_all * d * sizeof(float), hipMemcpyHostToDevice, s));
+  free_side(h, true);
+  std::vector<int32_t> perm_all;
+  if ((st = build_side(h, Qall, n_all, true, &perm_all)) != RK_OK) { cleanup(); return st; }
+  // 3. rows of the table gathered into that order: old users from their old
+  // sorted position, new users from step 1
+  std::vector<int64_t> pos_old(n_old), src(n_all);
+  for (int64_t i = 0; i < n_old; ++i) pos_old[perm_old[i]] = i;
+  for (int64_t i = 0; i < n_all; ++i) {
+    const int64_t o = perm_all[i];
+    src[i] = o < n_old ? pos_old[o] : -1 - (o - n_old);
+  }
+  int64_t* srcd = nullptr;
+  UTRY(talloc((void**)&srcd, (size_t)n_all * sizeof(int64_t)));
+  UTRY(hipMemcpyAsync(srcd, src.data(), n_all * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  double* L64o = h->L64;
+  float* L32o = h->L32;
+  h->L64 = nullptr;
+  h->L32 = nullptr;
+  UTRY(h->dalloc(&h->L64, (size_t)K * ix.n_pad));
+  UTRY(h->dalloc(&h->L32, (size_t)K * ix.n_pad));
+  launch_gather_bounds(K, n_all, ix.n_pad, srcd, L64o, L32o, old_pad, L64n, L32n, new_pad, h->L64, h->L32, s);
+  UTRY(hipGetLastError());
+  UTRY(hipStreamSynchronize(s));
+  ix.L64 = h->L64;
+  ix.L32 = h->L32;
+  h->dfree(L64o);
+  h->dfree(L32o);
+  cleanup();
+#undef UTRY
+  // 4. blocks over the grown order, and the workspaces sized by users
+  h->dfree(h->LB);
+  h->dfree(h->bnorm);
+  if ((st = build_blocks(h)) != RK_OK) return st;
+  free_user_ws(h);
+  if ((st = alloc_user_ws(h)) != RK_OK) return st;
+  h->bw.release();
+  h->updates++;
   h->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return RK_OK;
 }
@@ -1282,6 +1540,7 @@ rk_status rk_index_stats(const rk_index* hc, rk_stats* o) {
   o->build_cand_total = h->cand_total;
   o->build_cand_overflow_users = h->cand_ovf;
   o->rebuilds = h->rebuilds;
+  o->updates = h->updates;
   o->queries = h->queries;
   unsigned long long c[16] = {};
   HIPTRY(hipSetDevice(h->device));
@@ -1430,6 +1689,7 @@ rk_status rk_server_add_catalog(rk_server* s, rk_index* h, int32_t* catalog) {
   const int32_t ci = (int32_t)s->cats.size();
   *catalog = ci;
   s->cats.push_back(cat);
+  h->served++;
   for (ServerSlot* c : cat->slots) c->worker = std::thread([s, ci, cat, c] { s->loop(ci, cat, c); });
   return RK_OK;
 }

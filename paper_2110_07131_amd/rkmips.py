@@ -29,6 +29,7 @@ EXPORTS = [
     "rk_reverse_kmips_batch_dev_noalloc",
     "rk_index_set_counting", "rk_index_stats",
     "rk_index_reset_counters", "rk_index_export", "rk_index_rebuild", "rk_index_footprint",
+    "rk_index_add_items", "rk_index_add_users",
     "rk_index_free", "rk_last_error",
     "rk_server_opts_default", "rk_server_create", "rk_server_add_catalog", "rk_server_submit",
     "rk_server_poll", "rk_server_inflight", "rk_server_used_bytes", "rk_server_free",
@@ -66,7 +67,8 @@ class Stats(ctypes.Structure):
                 ("rechecks", ctypes.c_int64), ("results", ctypes.c_int64),
                 ("scan_long", ctypes.c_int64), ("scan_full_f64", ctypes.c_int64),
                 ("scan_handoff", ctypes.c_int64), ("scan_quarters", ctypes.c_int64),
-                ("scan_valu_tiles", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
+                ("scan_valu_tiles", ctypes.c_int64), ("updates", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 2)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -139,6 +141,9 @@ def lib():
     L.rk_index_export.restype = ctypes.c_int
     L.rk_index_rebuild.argtypes = [vp, i32]
     L.rk_index_rebuild.restype = ctypes.c_int
+    for f in (L.rk_index_add_items, L.rk_index_add_users):
+        f.argtypes = [vp, vp, i64]
+        f.restype = ctypes.c_int
     L.rk_index_footprint.argtypes = [i64, i64, i32, i32, ctypes.POINTER(BuildOpts)]
     L.rk_index_footprint.restype = i64
     L.rk_index_free.argtypes = [vp]
@@ -335,6 +340,18 @@ class Index:
     def rebuild(self, k_max: int):
         _check(lib().rk_index_rebuild(self._h, int(k_max)))
         self.k_max = int(k_max)
+
+    def add_items(self, P):
+        """Append items (ids continue from m); see rk_index_add_items."""
+        P = _f32(P).reshape(-1, self.d)
+        _check(lib().rk_index_add_items(self._h, _ptr(P), P.shape[0]))
+        self.m += P.shape[0]
+
+    def add_users(self, Q):
+        """Append users (ids continue from n); see rk_index_add_users."""
+        Q = _f32(Q).reshape(-1, self.d)
+        _check(lib().rk_index_add_users(self._h, _ptr(Q), Q.shape[0]))
+        self.n += Q.shape[0]
 
     def export(self, field: int) -> np.ndarray:
         st = self.stats()
