@@ -619,14 +619,28 @@ __global__ void __launch_bounds__(256, (!BF16 && NV <= 4) ? 4 : 2) k_bfilter(Dev
         c_rest += __popc(rest);
         c_yes += __popc(yes);
       }
-      // ---- certified members: result bits
-      uint32_t yy = yes;
-      while (yy) {
-        const int r = __ffs(yy) - 1;
-        yy &= yy - 1;
-        const int32_t jo = bv.perm[(int64_t)T * TILE + quarter_row(qhalf, half, r)];
-        atomicOr(&bv.bits[(int64_t)jo * bv.W + (orig_u >> 5)], 1u << (orig_u & 31));
-        atomicAdd(&bv.counts[jo], 1ull);
+      // ---- certified members: result bits and counts.  The wave goes over
+      // the rows that hold any result (a lane's row r is row
+      // (r/4)*8 + half*4 + r%4 of the quarter; lane l < 32 loads the
+      // caller-order index of row l once), with one count update per row and
+      // wave half instead of one per result, which the row's lanes would all
+      // make to one address.  Same-box A/B: 50k users x 10k items, 312 ->
+      // 270 us per 4,096 queries; 100k x 20k in bf16, 277 -> 216 us per
+      // 4,000; 500k x 50k at d = 200 in bf16 (fewer results per row) 2%
+      // slower.
+      if (__ballot(yes != 0u)) {
+        const int32_t jrow = bv.perm[(int64_t)T * TILE + qhalf * 32 + (lane & 31)];
+        uint32_t any = yes;
+        for (int off = 32; off > 0; off >>= 1) any |= __shfl_xor(any, off);
+        while (any) {
+          const int r = __ffs(any) - 1;
+          any &= any - 1;
+          const unsigned long long b = __ballot((yes >> r) & 1u);
+          const int32_t jo = __shfl(jrow, (r / 4) * 8 + half * 4 + (r % 4));
+          if ((yes >> r) & 1u) atomicOr(&bv.bits[(int64_t)jo * bv.W + (orig_u >> 5)], 1u << (orig_u & 31));
+          const uint32_t c = __popc(half ? (uint32_t)(b >> 32) : (uint32_t)b);
+          if (col == 0 && c) atomicAdd(&bv.counts[jo], (unsigned long long)c);
+        }
       }
       // ---- undecided pairs: appended (one atomic per wave).  Exact table:
       // one flat list.  Bounded table: the wave fills chunks of its own, each
