@@ -106,6 +106,37 @@ __device__ __forceinline__ double dot64_rows(const float* __restrict__ x,
   return s;
 }
 
+// The same from rows of d4 float4s (16-byte aligned, d = 4 d4): the same
+// products summed in the same order, a quarter of the load instructions.
+__device__ __forceinline__ double dot64_rows4(const float4* __restrict__ x,
+                                              const float4* __restrict__ y, int d4) {
+  double s = 0.0;
+  int c0 = 0;
+  for (; c0 + 8 <= d4; c0 += 8) {
+    float4 xv[8], yv[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      xv[i] = x[c0 + i];
+      yv[i] = y[c0 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      s = fma((double)xv[i].x, (double)yv[i].x, s);
+      s = fma((double)xv[i].y, (double)yv[i].y, s);
+      s = fma((double)xv[i].z, (double)yv[i].z, s);
+      s = fma((double)xv[i].w, (double)yv[i].w, s);
+    }
+  }
+  for (; c0 < d4; ++c0) {
+    const float4 a = x[c0], b = y[c0];
+    s = fma((double)a.x, (double)b.x, s);
+    s = fma((double)a.y, (double)b.y, s);
+    s = fma((double)a.z, (double)b.z, s);
+    s = fma((double)a.w, (double)b.w, s);
+  }
+  return s;
+}
+
 // |approx - f| <= margin(|u|^, |x|^) for every bulk inner product.
 __device__ __forceinline__ float margin(const DevIndex& ix, float nu, float nx) {
   return ix.eps_rel * (nu * nx) + ix.eps_abs;
