@@ -174,3 +174,37 @@ def test_update_of_a_served_index_is_refused():
     idx.add_items(P[:5])  # the server is gone
     assert idx.stats()["m"] == 105
     idx.free()
+
+
+def test_device_entry_points_after_updates():
+    # the device batch calls (own workspace, and the static one of the entry
+    # point that allocates nothing) size their work by the grown catalog
+    import torch
+    rng = np.random.default_rng(67)
+    d = 16
+    Q = datagen.vectors(1500, d, 0.5, rng)
+    P = datagen.vectors(400, d, 0.5, rng)
+    idx = Index.build(Q, P, 8)
+    Q1, P1 = datagen.vectors(2600, d, 0.5, rng), datagen.vectors(350, d, 0.5, rng)
+    idx.add_users(Q1)
+    idx.add_items(P1)
+    Q, P = np.vstack([Q, Q1]), np.vstack([P, P1])
+    qs_np = np.vstack([P1[:40], datagen.vectors(24, d, 0.5, rng)])
+    ks = rng.integers(1, 9, len(qs_np)).astype(np.int32)
+    th = oracle.theta(Q, P, 8)
+    qs = torch.from_numpy(np.ascontiguousarray(qs_np)).cuda()
+    stream = torch.cuda.Stream()
+    outs = []
+    for f in (idx.reverse_kmips_batch_dev, idx.reverse_kmips_batch_dev_noalloc):
+        off = torch.empty(len(ks) + 1, dtype=torch.int64, device="cuda")
+        ids = torch.empty(len(ks) * Q.shape[0], dtype=torch.int32, device="cuda")
+        f(qs, ks, off, ids, stream.cuda_stream)
+        torch.cuda.synchronize()
+        off_h = off.cpu().numpy()
+        outs.append((off_h, ids[:int(off_h[-1])].cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    off_h, ids_h = outs[0]
+    for i in range(len(ks)):
+        want = oracle.theta_query(th, Q, qs_np[i], int(ks[i]))
+        assert np.array_equal(ids_h[off_h[i]:off_h[i + 1]], want), i
+    idx.free()
